@@ -152,8 +152,9 @@ def leapfrog(x0, v0, m, eps2: float, dt: float, steps: int, trajectory: bool = F
     return (x, v, traj) if trajectory else (x, v)
 
 
-def leapfrog_vjp(x0, v0, m, eps2: float, dt: float, steps: int, u):
-    """Gradients of L = sum_i u_i . x_i(T) with respect to x0, v0 and m.
+def leapfrog_vjp(x0, v0, m, eps2: float, dt: float, steps: int, u, uv=None):
+    """Gradients of L = sum_i u_i . x_i(T) + uv_i . v_i(T) with respect to
+    x0, v0 and m (``uv`` None means the loss ignores the final velocities).
 
     Reverse sweep of one step (x, v) -> (x', v'), with g = -a:
         v_half = v + (dt/2) g(x);  x' = x + dt v_half;  v' = v_half + (dt/2) g(x')
@@ -169,7 +170,7 @@ def leapfrog_vjp(x0, v0, m, eps2: float, dt: float, steps: int, u):
     _, _, traj = leapfrog(x0, v0, m, eps2, dt, steps, trajectory=True)
     n = traj.shape[1]
     lx = _d(u, (n, 3)).copy()   # adjoint of x_T
-    lv = np.zeros((n, 3))       # adjoint of v_T (the loss ignores v_T)
+    lv = np.zeros((n, 3)) if uv is None else _d(uv, (n, 3)).copy()   # adjoint of v_T
     lm = np.zeros(n)
     half = 0.5 * dt
     # Weight on g(x_t) owed by the start kick of step t (none for t = T).

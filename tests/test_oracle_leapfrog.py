@@ -80,3 +80,24 @@ def test_reverse_sweep_matches_directional_differences():
               - L(x0 - h * dx, v0 - h * dv, m - h * dm)) / (2 * h)
         an = np.sum(gx * dx) + np.sum(gv * dv) + np.sum(gm * dm)
         assert fd == pytest.approx(an, rel=1e-6), which
+
+
+def test_reverse_sweep_with_final_velocity_weight():
+    n, steps, dt, eps2, h = 16, 9, 2e-2, 5e-2, 1e-6
+    g = np.random.default_rng(4)
+    x0 = g.standard_normal((n, 3))
+    v0 = 0.3 * g.standard_normal((n, 3))
+    m = g.uniform(0.02, 0.1, n)
+    u = g.standard_normal((n, 3))
+    uv = g.standard_normal((n, 3))
+    gx, gv, gm = R.leapfrog_vjp(x0, v0, m, eps2, dt, steps, u, uv)
+
+    def L(x, v, mm):
+        xT, vT = R.leapfrog(x, v, mm, eps2, dt, steps)
+        return float(np.sum(u * xT) + np.sum(uv * vT))
+
+    dx, dv, dm = (g.standard_normal(x0.shape), g.standard_normal(v0.shape),
+                  g.standard_normal(m.shape))
+    fd = (L(x0 + h * dx, v0 + h * dv, m + h * dm) - L(x0 - h * dx, v0 - h * dv, m - h * dm)) / (2 * h)
+    an = np.sum(gx * dx) + np.sum(gv * dv) + np.sum(gm * dm)
+    assert fd == pytest.approx(an, rel=1e-6)
