@@ -1,0 +1,258 @@
+"""Throughput of the exact softened all-pairs sum on one MI355X.
+
+One step is one evaluation of Eq. (gravity) (a_i and p_i for every i, j != i)
+on a 2^20-particle Plummer sphere with log-normal masses and eps^2 = 1e-6,
+inputs resident in HBM.  The JSON line also reports the adjoint
+(nbody_forces_backward on a 16,384-particle Plummer sphere) and the batched
+ensemble (4,096 Plummer systems of 8..2048 particles in one persistent
+launch, against one plain launch per system), the roofline position of the
+forward kernel, and the FP64 CPU reference timed on a bounded sample of the
+same workload on this host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-interactions/s & % FP32 VALU peak (38 flop/pair): fwd, adjoint, batched"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_plummer_n1048576_traffic.txt")
+FORWARD_SOURCES = [os.path.join(ROOT, "paper_0904_3659_amd", "csrc", f)
+                   for f in ("forward.hip", "common.hpp")]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def forward_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in FORWARD_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the forward kernel from the committed counter
+    summary, or None if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != forward_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_calls(fn, reps: int, torch):
+    """Run fn() reps times; per-call HIP-event durations (ms) on the current
+    stream (where the library launches) and the wall time of the whole loop."""
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in evs], wall
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """The FP64 oracle on a bounded row sample of the same workload."""
+    from oracle import reference as R
+    from paper_0904_3659_amd import inputs
+    n = w.n
+    rows = inputs.check_rows(n, 65536, (3, 3))
+    probe = rows[:64]
+    t0 = time.perf_counter()
+    R.forces_rows(w.x, w.m, w.eps2, probe)
+    dt = time.perf_counter() - t0
+    per_row = dt / probe.size
+    count = int(min(rows.size, max(64, budget_s / max(per_row, 1e-9))))
+    sample = rows[:count]
+    t0 = time.perf_counter()
+    R.forces_rows(w.x, w.m, w.eps2, sample)
+    dt = time.perf_counter() - t0
+    pairs = count * (n - 1)
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": R.num_threads(),
+            "kind": "oracle",
+            "sample": f"{count} seeded rows x {n - 1} j of {w.name}, FP64, {dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    ap.add_argument("--only-forward", action="store_true", help="skip adjoint and batched legs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device-to-device copy of BYTES (the reference "
+                         "kernel that scales the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_0904_3659_amd import inputs, metrics
+    from paper_0904_3659_amd import nbody as nb
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {src.numel() * 4} bytes copied")
+        del src, dst
+
+    # ---------------------------------------------------------- forward, 2^20
+    log("generating plummer_n1048576 inputs")
+    w = inputs.plummer_1m_lognormal()
+    x = torch.from_numpy(w.x).to(dev)
+    m = torch.from_numpy(w.m).to(dev)
+    a = torch.empty((w.n, 3), device=dev)
+    p = torch.empty((w.n,), device=dev)
+    fwd = lambda: nb.forces(x, m, w.eps2, out=(a, p))
+    log(f"forward warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        fwd()
+    torch.cuda.synchronize()
+    log(f"forward timed x{args.steps}")
+    per_call, wall = timed_calls(fwd, args.steps, torch)
+    pairs = metrics.pairs(w.n)
+    ms_step = wall * 1e3 / args.steps
+    value = pairs / (wall / args.steps)
+    kern_ms = float(np.mean(per_call))
+    achieved = pairs * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3) / 1e12
+    peak = metrics.MI355X_FP32_VECTOR_TFLOPS
+    traffic = read_traffic()
+    variant = nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, w.n)]
+    log(f"forward {ms_step:.2f} ms/step, {value:.3e} pairs/s, kernel {kern_ms:.2f} ms")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "eps2": w.eps2, "pairs_per_step": pairs,
+                   "variant": variant},
+        "frac_fp32_peak_38flop": value * metrics.FLOP_PER_PAIR / (peak * 1e12),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": variant, "kernel_ms": kern_ms,
+                     "flop_per_pair": metrics.FLOP_PER_PAIR},
+    }
+
+    if not args.only_forward:
+        # ------------------------------------------------------ adjoint, 16k
+        log("adjoint leg")
+        wa = inputs.adjoint_16k()
+        xa = torch.from_numpy(wa.x).to(dev)
+        ma = torch.from_numpy(wa.m).to(dev)
+        ga = torch.from_numpy(wa.extra["w"]).to(dev)
+        gp = torch.from_numpy(wa.extra["v"]).to(dev)
+        gx = torch.empty_like(xa)
+        gm = torch.empty_like(ma)
+        bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
+        for _ in range(3):
+            bwd()
+        per, wall_a = timed_calls(bwd, 20, torch)
+        pa = metrics.pairs(wa.n)
+        ka = float(np.median(per))
+        out["adjoint"] = {
+            "workload": wa.name, "pairs_per_s": pa / (wall_a / 20), "kernel_ms": ka,
+            "pairs_per_s_kernel": pa / (ka * 1e-3),
+            "frac_fp32_peak_38flop": pa / (ka * 1e-3) * 38 / (peak * 1e12),
+            "frac_fp32_peak_own_flop": pa / (ka * 1e-3) * 68 / (peak * 1e12),
+            "own_flop_per_pair": 68,
+            "variant": nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)],
+        }
+        log(f"adjoint {ka:.3f} ms")
+
+        # ------------------------------------------------------ batched
+        log("batched leg")
+        ens = inputs.ensemble_4096()
+        xb = torch.from_numpy(ens.x).to(dev)
+        mb = torch.from_numpy(ens.m).to(dev)
+        ab = torch.empty_like(xb)
+        pb = torch.empty_like(mb)
+        t0 = time.perf_counter()
+        nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
+        for _ in range(2):
+            bat()
+        per_b, wall_b = timed_calls(bat, 10, torch)
+        views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
+                 for lo, hi in zip(ens.offsets[:-1], ens.offsets[1:]) if hi > lo]
+
+        def plain():
+            for xs, ms, as_, ps in views:
+                nb.forces(xs, ms, ens.eps2, out=(as_, ps))
+
+        plain()
+        _, wall_plain = timed_calls(plain, 1, torch)
+        pb_pairs = metrics.pairs_ensemble(ens.sizes())
+        kb = float(np.median(per_b))
+        out["batched"] = {
+            "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
+            "pairs": pb_pairs, "persistent_ms": kb, "pairs_per_s": pb_pairs / (kb * 1e-3),
+            "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
+            "plain_launches_ms": wall_plain * 1e3,
+            "speedup_vs_plain": wall_plain * 1e3 / kb,
+            "plan_build_s": plan_s,
+            "variant": nb.variant_names(nb.BATCHED)[nb.selected_variant(nb.BATCHED, int(np.mean(ens.sizes())))],
+        }
+        log(f"batched {kb:.3f} ms vs plain {wall_plain * 1e3:.1f} ms")
+
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(w)
+    else:
+        out["cpu_baseline"] = None
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

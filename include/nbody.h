@@ -1,0 +1,173 @@
+/*
+ * nbody.h -- C ABI of libnbody.so: the exact softened all-pairs gravity sum
+ * of Fujiwara & Nakasato, "Fast Simulations of Gravitational Many-body
+ * Problem on RV770 GPU" (arXiv:0904.3659), on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are device pointers (memory of the current HIP device), float32,
+ *   row-major, densely packed: positions x[n][3], masses m[n], accelerations
+ *   a[n][3], potentials p[n].  The caller owns every array; the library never
+ *   frees or retains caller memory beyond the call.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *   is asynchronous with respect to the host and ordered on `stream`; faults
+ *   inside a kernel surface at the caller's next synchronisation.
+ * - Outputs are fully overwritten, never accumulated into.  Inputs and
+ *   outputs must not overlap (checked on the host from the address ranges).
+ * - Library workspace (partial sums, work lists) is device memory owned by
+ *   the library, cached per (device, stream) and grown on demand; it is held
+ *   until nbody_release_workspace() or process exit.  Calls that share one
+ *   stream reuse it safely; calls on different streams use different
+ *   workspaces.
+ * - No C++ exception crosses this interface.  Every call returns a status;
+ *   on failure nbody_last_error() gives a thread-local detail string.
+ *   Argument checks run before any HIP call, so an invalid call touches no
+ *   device state.
+ * - n is limited to NBODY_MAX_N particles (per system for the batched call,
+ *   and in total).
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBODY_ABI_VERSION 1
+#define NBODY_MAX_N (INT64_C(1) << 28)
+
+typedef enum nbody_status {
+    NBODY_OK = 0,
+    NBODY_ERROR_INVALID_ARGUMENT = 1,   /* bad size, pointer, eps2, offsets, overlap */
+    NBODY_ERROR_UNSUPPORTED_DEVICE = 2, /* current device is not gfx950 */
+    NBODY_ERROR_OUT_OF_MEMORY = 3,      /* workspace allocation failed */
+    NBODY_ERROR_LAUNCH_FAILED = 4,      /* a kernel launch was rejected */
+    NBODY_ERROR_INTERNAL = 5            /* any other HIP runtime error */
+} nbody_status;
+
+/* Kinds of evaluation, for variant selection and tuning. */
+typedef enum nbody_kind {
+    NBODY_KIND_FORWARD = 0,
+    NBODY_KIND_BACKWARD = 1,
+    NBODY_KIND_BATCHED = 2
+} nbody_kind;
+
+/* NBODY_ABI_VERSION of the built library. */
+int nbody_abi_version(void);
+
+/* Static, never-NULL name of a status code. */
+const char *nbody_status_string(nbody_status status);
+
+/* Thread-local detail of the last failed call on this thread ("" if none). */
+const char *nbody_last_error(void);
+
+/*
+ * Forward evaluation, Eq. (gravity) of Sec. I, in the paper's sign:
+ *     a_i = sum_{j != i} m_j (x_i - x_j) / (|x_i - x_j|^2 + eps2)^(3/2)
+ *     p_i = sum_{j != i} m_j / (|x_i - x_j|^2 + eps2)^(1/2)
+ * (a points from x_j towards x_i, p is positive; the physical acceleration
+ * is -a).  G = 1.  The term j == i is excluded by index, so no self
+ * potential m_i/eps appears.  One softening eps2 = eps^2 serves every pair.
+ *
+ * x: [n][3] in, m: [n] in, a: [n][3] out, p: [n] out (p may be NULL to skip
+ * the potential store; the sum is still formed).
+ * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
+ * root, and partial sums folded per j-tile (two-level accumulation).
+ * The result is bitwise reproducible for a fixed n, variant and device.
+ *
+ * Errors: n < 0 or n > NBODY_MAX_N, NULL x/m/a with n > 0, eps2 negative or
+ * not finite, overlapping arrays -> INVALID_ARGUMENT.  n == 0 -> OK, nothing
+ * launched.  n == 1 -> a = 0, p = 0.  eps2 == 0 is allowed; then two distinct
+ * particles at the same position give inf/NaN (IEEE), not an error.  NaN or
+ * inf inside x or m is not checked and propagates.
+ */
+nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
+                          float *a, float *p, void *stream);
+
+/*
+ * Backward (vector-Jacobian product) of nbody_forces, derived from
+ * Eq. (gravity) by the chain rule.  For upstream gradients grad_a = dL/da
+ * [n][3] and grad_p = dL/dp [n], with d = x_k - x_j, s = |d|^2 + eps2,
+ * r = s^(-1/2), c_kj = m_j grad_a_k - m_k grad_a_j,
+ * b_kj = m_j grad_p_k + m_k grad_p_j:
+ *     grad_x_k = sum_{j != k} r^3 [ c_kj - (3 r^2 (c_kj . d) + b_kj) d ]
+ *     grad_m_k = sum_{j != k} r [ grad_p_j - r^2 (grad_a_j . d) ]
+ *
+ * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
+ * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
+ * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
+                                   const float *grad_a, const float *grad_p,
+                                   float *grad_x, float *grad_m, void *stream);
+
+/*
+ * Eq. (gravity) on many independent systems in one launch.  System s owns
+ * particles [offsets[s], offsets[s+1]) of x, m, a, p and interacts only with
+ * itself.  `offsets` is a HOST array of num_systems + 1 int64 values with
+ * offsets[0] == 0, non-decreasing; the total is offsets[num_systems].
+ * Empty systems are allowed.  The library builds a work plan from the
+ * offsets (cost-ordered list of (system, i-tile) units), caches it keyed by
+ * the offsets' content, uploads it to library workspace and runs one
+ * persistent launch.  Per-system results equal nbody_forces on that system
+ * up to float32 summation order, and are bitwise independent of the other
+ * systems' contents.
+ *
+ * Errors: num_systems < 0, NULL offsets, offsets[0] != 0, a decreasing
+ * offset, a system or the total above NBODY_MAX_N -> INVALID_ARGUMENT; plus
+ * the pointer, eps2 and overlap rules of nbody_forces.
+ */
+nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems,
+                                  const float *x, const float *m, float eps2,
+                                  float *a, float *p, void *stream);
+
+/*
+ * Leap-frog kick and drift (Eqs. (1)-(3) of Sec. III) as device kernels, so
+ * an integrator can stay on the device between force evaluations:
+ *     nbody_axpy:  y[t] += alpha * xv[t]   for t < len   (float32 FMA)
+ * A kick with the paper's a is nbody_axpy(v, a, -dt/2) (the physical
+ * acceleration is -a); a drift is nbody_axpy(x, v, dt).
+ * Errors: len < 0, NULL with len > 0, alpha not finite, overlap ->
+ * INVALID_ARGUMENT.
+ */
+nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, void *stream);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Number of compiled kernel variants for a kind (0 for an unknown kind). */
+int nbody_variant_count(int kind);
+
+/* Static name of variant `index` of `kind` (NULL if out of range). */
+const char *nbody_variant_name(int kind, int index);
+
+/*
+ * Force variant `index` for `kind` on this process (-1 restores automatic
+ * choice).  The environment variable NBODY_VARIANT=<kind>:<index>[,...]
+ * sets the same at load time.  Out-of-range index -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_set_variant(int kind, int index);
+
+/*
+ * Time every variant of `kind` on each size in sizes[count] (synthetic
+ * inputs in library workspace, HIP events on `stream`) and record the
+ * fastest per size bucket in the in-process tuning table; if the
+ * environment variable NBODY_TUNE_CACHE names a file, the table is also
+ * written there as JSON and read back at load time.  Blocks the host until
+ * the timing runs finish.  For NBODY_KIND_BATCHED each size is the number of
+ * particles per system of a uniform ensemble holding about 2^22 particles.
+ */
+nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void *stream);
+
+/* Variant index the library would use for `kind` at size n (-1 on error). */
+int nbody_selected_variant(int kind, int64_t n);
+
+/* Free every cached workspace of every device and stream (synchronises). */
+nbody_status nbody_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

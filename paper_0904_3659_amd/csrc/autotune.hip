@@ -1,0 +1,127 @@
+// Variant timer: runs every compiled variant of a kind on synthetic inputs
+// of each requested size, times it with HIP events on the caller's stream
+// and records the fastest in the tuning table (bucketed by log2 of the
+// size).  The paper notes that the depth of loop unrolling decides the
+// speed (Sec. VII); here the choice is measured instead of fixed.
+#include "common.hpp"
+
+#include <algorithm>
+#include <vector>
+
+namespace nbody {
+namespace {
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+struct DeviceBuffers {
+    std::vector<void *> ptrs;
+    ~DeviceBuffers()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    nbody_status alloc(size_t bytes, float **out)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(autotune inputs)");
+        ptrs.push_back(p);
+        *out = static_cast<float *>(p);
+        return NBODY_OK;
+    }
+};
+
+template <class Run>
+nbody_status time_best(int count, hipStream_t stream, Run run, int *best)
+{
+    Events ev;
+    hipError_t e = hipEventCreate(&ev.a);
+    if (e == hipSuccess) e = hipEventCreate(&ev.b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    float best_ms = 0.f;
+    *best = -1;
+    for (int v = 0; v < count; ++v) {
+        nbody_status st = run(v);  // warm-up (also builds any plan)
+        if (st != NBODY_OK) return st;
+        float min_ms = -1.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            if ((e = hipEventRecord(ev.a, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((st = run(v)) != NBODY_OK) return st;
+            if ((e = hipEventRecord(ev.b, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((e = hipEventSynchronize(ev.b)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess)
+                return hip_fail(e, "hipEventElapsedTime");
+            if (min_ms < 0.f || ms < min_ms) min_ms = ms;
+            if (ms > 200.f) break;  // long runs: one timing is enough
+        }
+        if (*best < 0 || min_ms < best_ms) {
+            best_ms = min_ms;
+            *best = v;
+        }
+    }
+    return NBODY_OK;
+}
+
+}  // namespace
+
+nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int64_t count,
+                          hipStream_t stream)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t size = sizes[k];
+        DeviceBuffers buf;
+        nbody_status st;
+        int best = -1;
+        if (kind == NBODY_KIND_BATCHED) {
+            const int64_t ns = size;
+            const int64_t systems = std::max<int64_t>(1, ((int64_t)1 << 22) / ns);
+            const int n = (int)(ns * systems);
+            std::vector<int64_t> offsets(systems + 1);
+            for (int64_t s = 0; s <= systems; ++s) offsets[s] = s * ns;
+            float *x, *m, *a, *p;
+            if ((st = buf.alloc(12 * (size_t)n, &x)) || (st = buf.alloc(4 * (size_t)n, &m)) ||
+                (st = buf.alloc(12 * (size_t)n, &a)) || (st = buf.alloc(4 * (size_t)n, &p)))
+                return st;
+            if ((st = fill_synthetic(x, m, nullptr, nullptr, n, 7u, stream)) != NBODY_OK) return st;
+            st = time_best(batched_variant_count(), stream, [&](int v) {
+                return batched_run(v, dev, offsets.data(), systems, x, m, 1e-4f, a, p, stream);
+            }, &best);
+            if (st != NBODY_OK) return st;
+            record_tuned_variant(kind, ns, best);
+            continue;
+        }
+        const int n = (int)size;
+        float *x, *m, *a, *p;
+        if ((st = buf.alloc(12 * (size_t)n, &x)) || (st = buf.alloc(4 * (size_t)n, &m)) ||
+            (st = buf.alloc(12 * (size_t)n, &a)) || (st = buf.alloc(4 * (size_t)n, &p)))
+            return st;
+        if (kind == NBODY_KIND_FORWARD) {
+            if ((st = fill_synthetic(x, m, nullptr, nullptr, n, 11u, stream)) != NBODY_OK) return st;
+            st = time_best(forward_variant_count(), stream, [&](int v) {
+                return forward_run(v, dev, x, m, n, 1e-4f, a, p, stream);
+            }, &best);
+        } else {
+            float *w, *vv, *gx, *gm;
+            if ((st = buf.alloc(12 * (size_t)n, &w)) || (st = buf.alloc(4 * (size_t)n, &vv)) ||
+                (st = buf.alloc(12 * (size_t)n, &gx)) || (st = buf.alloc(4 * (size_t)n, &gm)))
+                return st;
+            if ((st = fill_synthetic(x, m, w, vv, n, 13u, stream)) != NBODY_OK) return st;
+            st = time_best(backward_variant_count(), stream, [&](int v) {
+                return backward_run(v, dev, x, m, n, 1e-4f, w, vv, gx, gm, stream);
+            }, &best);
+        }
+        if (st != NBODY_OK) return st;
+        record_tuned_variant(kind, n, best);
+        // buffers are freed by hipFree (which waits for the device)
+    }
+    return NBODY_OK;
+}
+
+}  // namespace nbody

@@ -1,0 +1,252 @@
+// Eq. (gravity) (Sec. I) on many independent systems in one persistent
+// launch, float32 on gfx950.
+//
+// Plan (host, built once per offsets content and cached):
+//   every non-empty system s is cut into i-tiles of BLOCK particles; each
+//   (system, i-tile) is a work unit {i_begin, i_end, j_begin, j_end} in
+//   absolute particle indices.  A unit's cost is BLOCK lanes times its
+//   system's padded j count, so units are sorted by decreasing cost
+//   (largest first; ties keep system order) and dealt to the resident
+//   workgroups in a snake order (g, 2G-1-g, 2G+g, ...), which balances the
+//   static schedule without atomics or counters.
+//
+// Kernel: a grid of exactly as many workgroups as the device holds at once;
+// workgroup g walks its units, staging each system's j-range through LDS
+// in BLOCK-particle tiles with the same masked/unmasked split, register
+// i-rows and two-level accumulation as the single-system kernel.  Systems
+// never read one another's particles, so a system's result does not depend
+// on the rest of the batch.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+namespace nbody {
+namespace {
+
+struct Unit {
+    int i_begin, i_end, j_begin, j_end;
+};
+
+struct BatArgs {
+    const int4 *units;
+    int num_units;
+    const float *x;
+    const float *m;
+    float eps2;
+    float *a;
+    float *p;
+};
+
+template <int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void batched_kernel(BatArgs P)
+{
+    constexpr int TILE = BLOCK;
+    __shared__ float4 tile[TILE];
+    const int tid = threadIdx.x;
+    const int G = gridDim.x;
+    const int g = blockIdx.x;
+    const float eps2 = P.eps2;
+
+    for (int round = 0;; ++round) {
+        const int idx = (round & 1) ? round * G + (G - 1 - g) : round * G + g;
+        if (idx >= P.num_units) break;
+        const int4 w = P.units[idx];
+        const int i0 = w.x, iend = w.y, jbeg = w.z, jend = w.w;
+
+        const int i = i0 + tid;
+        const int ic = i < iend ? i : iend - 1;
+        const float xi = P.x[3 * ic], yi = P.x[3 * ic + 1], zi = P.x[3 * ic + 2];
+        float ax = 0.f, ay = 0.f, az = 0.f, pp = 0.f;
+
+        float4 next = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (jbeg + tid < jend) {
+            const int j = jbeg + tid;
+            next = make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j]);
+        }
+        for (int t0 = jbeg; t0 < jend; t0 += TILE) {
+            __syncthreads();
+            tile[tid] = next;
+            __syncthreads();
+            {
+                const int j = t0 + TILE + tid;
+                next = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (j < jend) next = make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j]);
+            }
+            float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
+            const int cnt = min(TILE, jend - t0);
+            const bool masked = (cnt < TILE) || (t0 < i0 + BLOCK && t0 + TILE > i0);
+            if (!masked) {
+                for (int jj = 0; jj < TILE; jj += U) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        pair_term(xi, yi, zi, tile[jj + u], eps2, tx, ty, tz, tp);
+                }
+            } else {
+                for (int jj = 0; jj < cnt; ++jj)
+                    pair_term_masked(xi, yi, zi, tile[jj], eps2, t0 + jj == i, tx, ty, tz, tp);
+            }
+            ax += tx;
+            ay += ty;
+            az += tz;
+            pp += tp;
+        }
+        if (i < iend) {
+            P.a[3 * i + 0] = ax;
+            P.a[3 * i + 1] = ay;
+            P.a[3 * i + 2] = az;
+            if (P.p) P.p[i] = pp;
+        }
+    }
+}
+
+using KernelFn = void (*)(BatArgs);
+
+struct Variant {
+    const char *name;
+    int block, unroll;
+    KernelFn fn;
+};
+
+#define BAT_VARIANT(B, U) {"bat_b" #B "_u" #U, B, U, batched_kernel<B, U>}
+
+const Variant kVariants[] = {
+    BAT_VARIANT(64, 8),
+    BAT_VARIANT(128, 8),
+    BAT_VARIANT(256, 8),
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// ---------------------------------------------------------------- plans
+
+struct Plan {
+    int device = -1;
+    int variant = -1;
+    std::vector<int64_t> offsets;  // exact key
+    int num_units = 0;
+    int grid = 0;
+    int4 *d_units = nullptr;
+    ~Plan()
+    {
+        if (d_units) (void)hipFree(d_units);
+    }
+};
+
+std::mutex g_plan_mu;
+std::vector<std::shared_ptr<Plan>> g_plans;  // most recent last
+constexpr size_t kMaxPlans = 8;
+
+nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
+                        int64_t num_systems, hipStream_t stream, std::shared_ptr<Plan> *out)
+{
+    const Variant &V = kVariants[variant];
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (size_t k = 0; k < g_plans.size(); ++k) {
+        Plan *pl = g_plans[k].get();
+        if (pl->device == dev.id && pl->variant == variant &&
+            pl->offsets.size() == (size_t)num_systems + 1 &&
+            std::memcmp(pl->offsets.data(), offsets, sizeof(int64_t) * (num_systems + 1)) == 0) {
+            // move to the back (most recently used)
+            std::shared_ptr<Plan> keep = g_plans[k];
+            g_plans.erase(g_plans.begin() + k);
+            g_plans.push_back(keep);
+            *out = keep;
+            return NBODY_OK;
+        }
+    }
+    auto plan = std::make_shared<Plan>();
+    plan->device = dev.id;
+    plan->variant = variant;
+    plan->offsets.assign(offsets, offsets + num_systems + 1);
+
+    struct Item {
+        int64_t cost;
+        int64_t order;
+        Unit u;
+    };
+    std::vector<Item> items;
+    int64_t order = 0;
+    for (int64_t s = 0; s < num_systems; ++s) {
+        const int64_t lo = offsets[s], hi = offsets[s + 1];
+        const int64_t ns = hi - lo;
+        if (ns <= 0) continue;
+        const int64_t padded_j = (ns + V.block - 1) / V.block * V.block;
+        for (int64_t t = lo; t < hi; t += V.block) {
+            Unit u{(int)t, (int)std::min<int64_t>(hi, t + V.block), (int)lo, (int)hi};
+            items.push_back(Item{padded_j, order++, u});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &p, const Item &q) { return p.cost > q.cost; });
+    std::vector<int4> host(items.size());
+    for (size_t k = 0; k < items.size(); ++k)
+        host[k] = make_int4(items[k].u.i_begin, items[k].u.i_end, items[k].u.j_begin,
+                            items[k].u.j_end);
+    plan->num_units = (int)host.size();
+
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.fn, V.block, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * dev.num_cu;
+    if (grid > plan->num_units) grid = plan->num_units;
+    plan->grid = (int)std::max<int64_t>(grid, 1);
+
+    if (plan->num_units > 0) {
+        if (fault_injected("alloc")) return fail(NBODY_ERROR_OUT_OF_MEMORY, "injected allocation fault");
+        e = hipMalloc(&plan->d_units, sizeof(int4) * host.size());
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(batched plan)");
+        e = hipMemcpyAsync(plan->d_units, host.data(), sizeof(int4) * host.size(),
+                           hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batched plan)");
+        // The host vector dies with this scope: wait for the copy.
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(batched plan)");
+    }
+    if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());  // hipFree syncs the device
+    g_plans.push_back(plan);
+    *out = plan;
+    return NBODY_OK;
+}
+
+}  // namespace
+
+int batched_variant_count() { return kNumVariants; }
+
+const char *batched_variant_name(int index)
+{
+    return (index >= 0 && index < kNumVariants) ? kVariants[index].name : nullptr;
+}
+
+int batched_default_variant(int64_t mean_n)
+{
+    if (mean_n >= 4096) return 2;
+    if (mean_n >= 512) return 1;
+    return 0;
+}
+
+void release_batched_plans()
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans.clear();
+}
+
+nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
+                         int64_t num_systems, const float *x, const float *m, float eps2,
+                         float *a, float *p, hipStream_t stream)
+{
+    std::shared_ptr<Plan> plan;
+    nbody_status st = build_plan(variant, dev, offsets, num_systems, stream, &plan);
+    if (st != NBODY_OK) return st;
+    if (plan->num_units == 0) return NBODY_OK;
+    const Variant &V = kVariants[variant];
+    BatArgs P{plan->d_units, plan->num_units, x, m, eps2, a, p};
+    if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    hipLaunchKernelGGL(V.fn, dim3(plan->grid), dim3(V.block), 0, stream, P);
+    return check_launch(V.name);
+}
+
+}  // namespace nbody

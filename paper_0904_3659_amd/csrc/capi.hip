@@ -1,0 +1,467 @@
+// C ABI of libnbody.so (declared in include/nbody.h): argument checks,
+// device checks, workspace cache, variant choice and tuning table.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace nbody {
+
+// ---------------------------------------------------------------- errors
+
+namespace {
+thread_local std::string t_last_error;
+}
+
+void clear_error() { t_last_error.clear(); }
+const char *last_error_cstr() { return t_last_error.c_str(); }
+
+nbody_status fail(nbody_status status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return status;
+}
+
+nbody_status hip_fail(hipError_t err, const char *what)
+{
+    const nbody_status st = (err == hipErrorOutOfMemory) ? NBODY_ERROR_OUT_OF_MEMORY
+                            : (err == hipErrorInvalidDeviceFunction || err == hipErrorLaunchFailure ||
+                               err == hipErrorInvalidConfiguration)
+                                ? NBODY_ERROR_LAUNCH_FAILED
+                                : NBODY_ERROR_INTERNAL;
+    return fail(st, "%s: %s (%d)", what, hipGetErrorString(err), (int)err);
+}
+
+nbody_status check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return NBODY_OK;
+    nbody_status st = hip_fail(e, what);
+    if (st == NBODY_ERROR_INTERNAL) st = NBODY_ERROR_LAUNCH_FAILED;
+    return st;
+}
+
+bool fault_injected(const char *what)
+{
+    const char *env = std::getenv("NBODY_FAULT");
+    return env && std::strcmp(env, what) == 0;
+}
+
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
+{
+    if (!a || !b || abytes == 0 || bbytes == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+// ---------------------------------------------------------------- devices
+
+namespace {
+struct DeviceState {
+    bool probed = false;
+    bool supported = false;
+    int num_cu = 0;
+    std::string arch;
+};
+std::mutex g_dev_mu;
+std::map<int, DeviceState> g_devices;
+}  // namespace
+
+nbody_status current_device(Device *dev)
+{
+    int id = -1;
+    hipError_t e = hipGetDevice(&id);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_dev_mu);
+    DeviceState &d = g_devices[id];
+    if (!d.probed) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, id);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        d.arch = prop.gcnArchName;
+        d.supported = d.arch.compare(0, 6, "gfx950") == 0;
+        d.num_cu = prop.multiProcessorCount;
+        d.probed = true;
+    }
+    if (!d.supported)
+        return fail(NBODY_ERROR_UNSUPPORTED_DEVICE, "device %d is %s; libnbody is built for gfx950",
+                    id, d.arch.c_str());
+    dev->id = id;
+    dev->num_cu = d.num_cu;
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+
+namespace {
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Buffer> g_ws;
+}  // namespace
+
+nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr)
+{
+    if (fault_injected("alloc")) return fail(NBODY_ERROR_OUT_OF_MEMORY, "injected allocation fault");
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    Buffer &b = g_ws[{dev.id, stream}];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            // hipFree waits for the device, so kernels still reading the old
+            // buffer on this stream finish first.
+            hipError_t e = hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+        }
+        const size_t grow = std::max(bytes, (size_t)1 << 20);
+        hipError_t e = hipMalloc(&b.ptr, grow);
+        if (e != hipSuccess) {
+            b.ptr = nullptr;
+            return hip_fail(e, "hipMalloc(workspace)");
+        }
+        b.bytes = grow;
+    }
+    *ptr = b.ptr;
+    return NBODY_OK;
+}
+
+// ---------------------------------------------------------------- variants
+
+namespace {
+std::mutex g_var_mu;
+int g_forced[3] = {-1, -1, -1};
+bool g_env_read = false;
+std::map<std::pair<int, int>, std::string> g_tuned;  // (kind, log2 bucket) -> variant name
+bool g_cache_read = false;
+
+int variant_count(int kind)
+{
+    switch (kind) {
+    case NBODY_KIND_FORWARD: return forward_variant_count();
+    case NBODY_KIND_BACKWARD: return backward_variant_count();
+    case NBODY_KIND_BATCHED: return batched_variant_count();
+    default: return 0;
+    }
+}
+
+const char *variant_name(int kind, int index)
+{
+    switch (kind) {
+    case NBODY_KIND_FORWARD: return forward_variant_name(index);
+    case NBODY_KIND_BACKWARD: return backward_variant_name(index);
+    case NBODY_KIND_BATCHED: return batched_variant_name(index);
+    default: return nullptr;
+    }
+}
+
+int bucket_of(int64_t n)
+{
+    int b = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// NBODY_VARIANT=<kind>:<index>[,<kind>:<index>...]
+void read_env_locked()
+{
+    if (g_env_read) return;
+    g_env_read = true;
+    const char *env = std::getenv("NBODY_VARIANT");
+    if (!env) return;
+    std::string s(env);
+    size_t pos = 0;
+    while (pos < s.size()) {
+        size_t end = s.find(',', pos);
+        if (end == std::string::npos) end = s.size();
+        int kind = -1, index = -1;
+        if (std::sscanf(s.substr(pos, end - pos).c_str(), "%d:%d", &kind, &index) == 2 &&
+            kind >= 0 && kind < 3 && index >= 0 && index < variant_count(kind))
+            g_forced[kind] = index;
+        pos = end + 1;
+    }
+}
+
+// Tuning cache file: one entry per line,
+//   {"kind": K, "bucket": B, "variant": "name"}
+void read_cache_locked()
+{
+    if (g_cache_read) return;
+    g_cache_read = true;
+    const char *path = std::getenv("NBODY_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        int kind = -1, bucket = -1;
+        char name[128] = {0};
+        const char *p = std::strstr(line, "\"kind\"");
+        if (!p) continue;
+        if (std::sscanf(p, "\"kind\": %d, \"bucket\": %d, \"variant\": \"%127[^\"]\"", &kind,
+                        &bucket, name) == 3)
+            g_tuned[{kind, bucket}] = name;
+    }
+    std::fclose(f);
+}
+
+void write_cache_locked()
+{
+    const char *path = std::getenv("NBODY_TUNE_CACHE");
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\"entries\": [\n");
+    size_t k = 0;
+    for (const auto &kv : g_tuned) {
+        std::fprintf(f, "  {\"kind\": %d, \"bucket\": %d, \"variant\": \"%s\"}%s\n", kv.first.first,
+                     kv.first.second, kv.second.c_str(), (++k < g_tuned.size()) ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+int index_of(int kind, const std::string &name)
+{
+    for (int k = 0; k < variant_count(kind); ++k)
+        if (name == variant_name(kind, k)) return k;
+    return -1;
+}
+}  // namespace
+
+int forced_variant(int kind)
+{
+    std::lock_guard<std::mutex> lock(g_var_mu);
+    read_env_locked();
+    return (kind >= 0 && kind < 3) ? g_forced[kind] : -1;
+}
+
+int tuned_variant(int kind, int64_t n)
+{
+    std::lock_guard<std::mutex> lock(g_var_mu);
+    read_cache_locked();
+    auto it = g_tuned.find({kind, bucket_of(n)});
+    if (it == g_tuned.end()) return -1;
+    return index_of(kind, it->second);
+}
+
+void record_tuned_variant(int kind, int64_t n, int index)
+{
+    std::lock_guard<std::mutex> lock(g_var_mu);
+    read_cache_locked();
+    g_tuned[{kind, bucket_of(n)}] = variant_name(kind, index);
+    write_cache_locked();
+}
+
+static int select_variant(int kind, int64_t n)
+{
+    int v = forced_variant(kind);
+    if (v >= 0) return v;
+    v = tuned_variant(kind, n);
+    if (v >= 0) return v;
+    switch (kind) {
+    case NBODY_KIND_FORWARD: return forward_default_variant(n);
+    case NBODY_KIND_BACKWARD: return backward_default_variant(n);
+    default: return batched_default_variant(n);
+    }
+}
+
+}  // namespace nbody
+
+using namespace nbody;
+
+// ====================================================================== ABI
+
+static bool bad_eps2(float eps2) { return !(eps2 >= 0.0f) || std::isinf(eps2); }
+
+extern "C" {
+
+int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
+
+const char *nbody_status_string(nbody_status status)
+{
+    switch (status) {
+    case NBODY_OK: return "NBODY_OK";
+    case NBODY_ERROR_INVALID_ARGUMENT: return "NBODY_ERROR_INVALID_ARGUMENT";
+    case NBODY_ERROR_UNSUPPORTED_DEVICE: return "NBODY_ERROR_UNSUPPORTED_DEVICE";
+    case NBODY_ERROR_OUT_OF_MEMORY: return "NBODY_ERROR_OUT_OF_MEMORY";
+    case NBODY_ERROR_LAUNCH_FAILED: return "NBODY_ERROR_LAUNCH_FAILED";
+    case NBODY_ERROR_INTERNAL: return "NBODY_ERROR_INTERNAL";
+    }
+    return "NBODY_ERROR_UNKNOWN";
+}
+
+const char *nbody_last_error(void) { return nbody::last_error_cstr(); }
+
+nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2, float *a,
+                          float *p, void *stream)
+{
+    clear_error();
+    if (n < 0 || n > NBODY_MAX_N)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld outside [0, %lld]", (long long)n,
+                    (long long)NBODY_MAX_N);
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    if (n == 0) return NBODY_OK;
+    if (!x || !m || !a) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x, m or a with n = %lld", (long long)n);
+    const size_t v3 = 12 * (size_t)n, v1 = 4 * (size_t)n;
+    if (overlaps(a, v3, x, v3) || overlaps(a, v3, m, v1) || overlaps(p, v1, x, v3) ||
+        overlaps(p, v1, m, v1) || overlaps(a, v3, p, v1))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "output arrays overlap each other or the inputs");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return forward_run(select_variant(NBODY_KIND_FORWARD, n), dev, x, m, (int)n, eps2, a, p,
+                       (hipStream_t)stream);
+}
+
+nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
+                                   const float *grad_a, const float *grad_p, float *grad_x,
+                                   float *grad_m, void *stream)
+{
+    clear_error();
+    if (n < 0 || n > NBODY_MAX_N)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld outside [0, %lld]", (long long)n,
+                    (long long)NBODY_MAX_N);
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    if (n == 0) return NBODY_OK;
+    if (!x || !m || !grad_x)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x, m or grad_x with n = %lld", (long long)n);
+    const size_t v3 = 12 * (size_t)n, v1 = 4 * (size_t)n;
+    const void *ins[4] = {x, m, grad_a, grad_p};
+    const size_t inb[4] = {v3, v1, v3, v1};
+    for (int k = 0; k < 4; ++k)
+        if (overlaps(grad_x, v3, ins[k], inb[k]) || overlaps(grad_m, v1, ins[k], inb[k]))
+            return fail(NBODY_ERROR_INVALID_ARGUMENT, "output arrays overlap the inputs");
+    if (overlaps(grad_x, v3, grad_m, v1))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "grad_x and grad_m overlap");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return backward_run(select_variant(NBODY_KIND_BACKWARD, n), dev, x, m, (int)n, eps2, grad_a,
+                        grad_p, grad_x, grad_m, (hipStream_t)stream);
+}
+
+nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, const float *x,
+                                  const float *m, float eps2, float *a, float *p, void *stream)
+{
+    clear_error();
+    if (num_systems < 0) return fail(NBODY_ERROR_INVALID_ARGUMENT, "num_systems = %lld < 0", (long long)num_systems);
+    if (!offsets) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL offsets");
+    if (offsets[0] != 0) return fail(NBODY_ERROR_INVALID_ARGUMENT, "offsets[0] = %lld, must be 0", (long long)offsets[0]);
+    for (int64_t s = 0; s < num_systems; ++s) {
+        const int64_t ns = offsets[s + 1] - offsets[s];
+        if (ns < 0)
+            return fail(NBODY_ERROR_INVALID_ARGUMENT, "offsets decrease at system %lld", (long long)s);
+        if (ns > NBODY_MAX_N || offsets[s + 1] > NBODY_MAX_N)
+            return fail(NBODY_ERROR_INVALID_ARGUMENT, "system %lld exceeds NBODY_MAX_N", (long long)s);
+    }
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    const int64_t n = offsets[num_systems];
+    if (n == 0) return NBODY_OK;
+    if (!x || !m || !a) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x, m or a with %lld particles", (long long)n);
+    const size_t v3 = 12 * (size_t)n, v1 = 4 * (size_t)n;
+    if (overlaps(a, v3, x, v3) || overlaps(a, v3, m, v1) || overlaps(p, v1, x, v3) ||
+        overlaps(p, v1, m, v1) || overlaps(a, v3, p, v1))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "output arrays overlap each other or the inputs");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    const int64_t mean_n = num_systems > 0 ? n / num_systems : 0;
+    return batched_run(select_variant(NBODY_KIND_BATCHED, mean_n), dev, offsets, num_systems, x,
+                       m, eps2, a, p, (hipStream_t)stream);
+}
+
+nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, void *stream)
+{
+    clear_error();
+    if (len < 0) return fail(NBODY_ERROR_INVALID_ARGUMENT, "len = %lld < 0", (long long)len);
+    if (!std::isfinite(alpha)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "alpha is not finite");
+    if (len == 0) return NBODY_OK;
+    if (!y || !xv) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL y or x with len = %lld", (long long)len);
+    if (overlaps(y, 4 * (size_t)len, xv, 4 * (size_t)len))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "y and x overlap");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return axpy_run(y, xv, len, alpha, (hipStream_t)stream);
+}
+
+int nbody_variant_count(int kind) { return variant_count(kind); }
+
+const char *nbody_variant_name(int kind, int index) { return variant_name(kind, index); }
+
+nbody_status nbody_set_variant(int kind, int index)
+{
+    clear_error();
+    if (kind < 0 || kind > 2) return fail(NBODY_ERROR_INVALID_ARGUMENT, "unknown kind %d", kind);
+    if (index < -1 || index >= variant_count(kind))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "variant %d out of range for kind %d", index, kind);
+    std::lock_guard<std::mutex> lock(g_var_mu);
+    read_env_locked();
+    g_forced[kind] = index;
+    return NBODY_OK;
+}
+
+int nbody_selected_variant(int kind, int64_t n)
+{
+    if (kind < 0 || kind > 2 || n < 0) return -1;
+    return select_variant(kind, n);
+}
+
+nbody_status nbody_release_workspace(void)
+{
+    clear_error();
+    release_batched_plans();
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    nbody_status st = NBODY_OK;
+    for (auto &kv : g_ws) {
+        if (kv.second.ptr) {
+            int cur = -1;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(kv.first.first);
+            hipError_t e = hipFree(kv.second.ptr);
+            (void)hipSetDevice(cur);
+            if (e != hipSuccess && st == NBODY_OK) st = hip_fail(e, "hipFree(workspace)");
+        }
+    }
+    g_ws.clear();
+    return st;
+}
+
+nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void *stream)
+{
+    clear_error();
+    if (kind < 0 || kind > 2) return fail(NBODY_ERROR_INVALID_ARGUMENT, "unknown kind %d", kind);
+    if (count < 0 || (count > 0 && !sizes)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "bad size list");
+    for (int64_t k = 0; k < count; ++k)
+        if (sizes[k] < 2 || sizes[k] > (1 << 22))
+            return fail(NBODY_ERROR_INVALID_ARGUMENT, "tuning size %lld outside [2, 2^22]", (long long)sizes[k]);
+    if (count == 0) return NBODY_OK;
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return autotune_run(kind, dev, sizes, count, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations shared by the translation units of libnbody.so.
+// Host side: status reporting, device checks, workspace cache, variant
+// tables.  Device side: the softened pair interaction of Eq. (gravity).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/nbody.h"
+
+namespace nbody {
+
+// ------------------------------------------------------------------ host
+
+// Record a failure for nbody_last_error() and return `status`.
+nbody_status fail(nbody_status status, const char *fmt, ...);
+// Map a HIP error to a status, recording `what` and the HIP message.
+nbody_status hip_fail(hipError_t err, const char *what);
+// Clear the thread-local error text (called at the start of each entry).
+void clear_error();
+
+struct Device {
+    int id = -1;
+    int num_cu = 0;
+};
+
+// Current HIP device; UNSUPPORTED_DEVICE unless it is a gfx950.
+nbody_status current_device(Device *dev);
+
+// Grow-only device buffer private to (device, stream).  The pointer stays
+// valid until the next workspace() call on the same (device, stream) that
+// asks for more bytes, or nbody_release_workspace().
+nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr);
+
+// NBODY_FAULT=<what> makes the named step report failure (tests of the
+// error paths; checked on the host before anything is launched).
+bool fault_injected(const char *what);
+
+// Check that [a, a+abytes) and [b, b+bbytes) are disjoint (NULL or empty
+// ranges never overlap).
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes);
+
+// Launch status of the last kernel launch on this thread.
+nbody_status check_launch(const char *what);
+
+// Forced variant (>= 0) for a kind, or -1 for automatic choice.
+int forced_variant(int kind);
+// Tuned variant for (kind, n) from the tuning table, or -1.
+int tuned_variant(int kind, int64_t n);
+void record_tuned_variant(int kind, int64_t n, int index);
+
+// ---- forward (Eq. (gravity))
+int forward_variant_count();
+const char *forward_variant_name(int index);
+int forward_default_variant(int64_t n);
+nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m,
+                         int n, float eps2, float *a, float *p, hipStream_t stream);
+
+// ---- backward (vector-Jacobian product of Eq. (gravity))
+int backward_variant_count();
+const char *backward_variant_name(int index);
+int backward_default_variant(int64_t n);
+nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m,
+                          int n, float eps2, const float *ga, const float *gp,
+                          float *gx, float *gm, hipStream_t stream);
+
+// ---- batched independent systems
+int batched_variant_count();
+const char *batched_variant_name(int index);
+int batched_default_variant(int64_t mean_n);
+nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
+                         int64_t num_systems, const float *x, const float *m, float eps2,
+                         float *a, float *p, hipStream_t stream);
+
+// ---- elementwise
+nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipStream_t stream);
+// Deterministic timing inputs (unit cube, masses 1/n, weights in [-1,1));
+// w and v may be NULL.
+nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint32_t seed,
+                            hipStream_t stream);
+
+// ---- variant timer (nbody_autotune)
+nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int64_t count,
+                          hipStream_t stream);
+
+// ---- errors
+const char *last_error_cstr();
+
+// ---- workspace release hooks of the batched plan cache
+void release_batched_plans();
+
+// ---------------------------------------------------------------- device
+
+// One term of Eq. (gravity): particle i at (xi, yi, zi) against
+// q = (x_j, y_j, z_j, m_j); adds m_j d r^3 to (ax, ay, az) and m_j r to pp,
+// with d = x_i - x_j and r = (|d|^2 + eps2)^(-1/2).  13 VALU operations plus
+// one hardware reciprocal square root (v_rsq_f32).
+__device__ __forceinline__ void pair_term(float xi, float yi, float zi, float4 q, float eps2,
+                                          float &ax, float &ay, float &az, float &pp)
+{
+    const float dx = xi - q.x;
+    const float dy = yi - q.y;
+    const float dz = zi - q.z;
+    float s = __builtin_fmaf(dx, dx, eps2);
+    s = __builtin_fmaf(dy, dy, s);
+    s = __builtin_fmaf(dz, dz, s);
+    const float r = __builtin_amdgcn_rsqf(s);
+    const float mr = q.w * r;
+    const float r2 = r * r;
+    const float mr3 = mr * r2;
+    pp += mr;
+    ax = __builtin_fmaf(mr3, dx, ax);
+    ay = __builtin_fmaf(mr3, dy, ay);
+    az = __builtin_fmaf(mr3, dz, az);
+}
+
+// The same term with the pair removed when `skip` holds (j == i, or a
+// padded slot): r is forced to 0 so every product vanishes exactly, also
+// for eps2 == 0 where the self distance would give an infinite r.
+__device__ __forceinline__ void pair_term_masked(float xi, float yi, float zi, float4 q,
+                                                 float eps2, bool skip, float &ax, float &ay,
+                                                 float &az, float &pp)
+{
+    const float dx = xi - q.x;
+    const float dy = yi - q.y;
+    const float dz = zi - q.z;
+    float s = __builtin_fmaf(dx, dx, eps2);
+    s = __builtin_fmaf(dy, dy, s);
+    s = __builtin_fmaf(dz, dz, s);
+    const float r = skip ? 0.0f : __builtin_amdgcn_rsqf(s);
+    const float mr = q.w * r;
+    const float r2 = r * r;
+    const float mr3 = mr * r2;
+    pp += mr;
+    ax = __builtin_fmaf(mr3, dx, ax);
+    ay = __builtin_fmaf(mr3, dy, ay);
+    az = __builtin_fmaf(mr3, dz, az);
+}
+
+}  // namespace nbody

@@ -1,0 +1,242 @@
+// Forward evaluation of Eq. (gravity) (Sec. I): a_i and p_i for every i,
+// j != i, float32, on gfx950.
+//
+// Work decomposition
+//   grid.x  : i-blocks of BLOCK*K particles; lane t of the workgroup keeps
+//             particles i0 + k*BLOCK + t (k < K) and their accumulators in
+//             VGPRs (the register-resident i-block; the paper's i-loop
+//             unrolling of Fig. sim-u, Sec. IV-A).
+//   grid.y  : j-splits; split s sums j in [s*chunk, min(n, (s+1)*chunk)).
+//             With more than one split, each writes a float4 partial
+//             (ax, ay, az, p) per i and a second kernel adds the splits in
+//             fixed order.
+//   j-tiles : BLOCK consecutive j are staged into LDS as float4 (x, y, z, m)
+//             -- the packing of x[n][3], m[n] happens here, one coalesced
+//             load per lane -- and read back by every lane as a broadcast.
+//             The next tile is fetched into registers while the current
+//             one is consumed.  The inner loop is unrolled U times over j
+//             (the paper's j-unrolling of Fig. double-u).
+//   accuracy: each tile's contribution is summed in fresh registers and
+//             folded into the running sum once per tile (two-level
+//             accumulation), which keeps the float32 error flat in n.
+//   self    : only tiles that intersect the workgroup's own i-range, and
+//             the ragged last tile, take the masked loop (index compare);
+//             every other tile runs unmasked.
+//
+// No atomics: the result is bitwise reproducible for a given variant, n
+// and split count.
+#include "common.hpp"
+
+#include <cstdio>
+
+namespace nbody {
+namespace {
+
+struct FwdArgs {
+    const float *x;
+    const float *m;
+    int n;
+    float eps2;
+    int chunk;        // j per split (a multiple of the tile size)
+    float4 *partial;  // [splits][n] when PARTIAL
+    float *a;
+    float *p;
+};
+
+template <int BLOCK, int K, int U, bool PARTIAL>
+__global__ __launch_bounds__(BLOCK) void forward_kernel(FwdArgs P)
+{
+    constexpr int TILE = BLOCK;
+    __shared__ float4 tile[TILE];
+
+    const int tid = threadIdx.x;
+    const int n = P.n;
+    const int i0 = blockIdx.x * (BLOCK * K);
+    const int jbeg = blockIdx.y * P.chunk;
+    const int jend = min(n, jbeg + P.chunk);
+    const float eps2 = P.eps2;
+
+    float xi[K], yi[K], zi[K];
+    int ii[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + k * BLOCK + tid;
+        ii[k] = i;
+        const int ic = i < n ? i : n - 1;  // idle lanes mirror a valid row
+        xi[k] = P.x[3 * ic + 0];
+        yi[k] = P.x[3 * ic + 1];
+        zi[k] = P.x[3 * ic + 2];
+    }
+    float ax[K], ay[K], az[K], pp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ax[k] = ay[k] = az[k] = pp[k] = 0.0f;
+
+    // j-tile prefetch registers
+    float4 next = make_float4(0.f, 0.f, 0.f, 0.f);
+    {
+        const int j = jbeg + tid;
+        if (j < jend) next = make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j]);
+    }
+
+    const int iblk_end = i0 + BLOCK * K;
+    for (int t0 = jbeg; t0 < jend; t0 += TILE) {
+        __syncthreads();  // previous tile fully consumed
+        tile[tid] = next;
+        __syncthreads();
+        {
+            const int j = t0 + TILE + tid;
+            next = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < jend) next = make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j]);
+        }
+
+        float tx[K], ty[K], tz[K], tp[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = tp[k] = 0.0f;
+
+        const int cnt = min(TILE, jend - t0);
+        const bool masked = (cnt < TILE) || (t0 < iblk_end && t0 + TILE > i0);
+        if (!masked) {
+            for (int jj = 0; jj < TILE; jj += U) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float4 q = tile[jj + u];
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        pair_term(xi[k], yi[k], zi[k], q, eps2, tx[k], ty[k], tz[k], tp[k]);
+                }
+            }
+        } else {
+            for (int jj = 0; jj < cnt; ++jj) {
+                const float4 q = tile[jj];
+                const int j = t0 + jj;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    pair_term_masked(xi[k], yi[k], zi[k], q, eps2, j == ii[k], tx[k], ty[k],
+                                     tz[k], tp[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ax[k] += tx[k];
+            ay[k] += ty[k];
+            az[k] += tz[k];
+            pp[k] += tp[k];
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ii[k];
+        if (i >= n) continue;
+        if (PARTIAL) {
+            P.partial[(size_t)blockIdx.y * n + i] = make_float4(ax[k], ay[k], az[k], pp[k]);
+        } else {
+            P.a[3 * i + 0] = ax[k];
+            P.a[3 * i + 1] = ay[k];
+            P.a[3 * i + 2] = az[k];
+            if (P.p) P.p[i] = pp[k];
+        }
+    }
+}
+
+// Sum the split partials of each row in split order and store a, p.
+__global__ __launch_bounds__(256) void reduce_splits_kernel(const float4 *__restrict__ partial,
+                                                            int splits, int n, float *a, float *p)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float4 s = partial[i];
+    for (int k = 1; k < splits; ++k) {
+        const float4 q = partial[(size_t)k * n + i];
+        s.x += q.x;
+        s.y += q.y;
+        s.z += q.z;
+        s.w += q.w;
+    }
+    a[3 * i + 0] = s.x;
+    a[3 * i + 1] = s.y;
+    a[3 * i + 2] = s.z;
+    if (p) p[i] = s.w;
+}
+
+using KernelFn = void (*)(FwdArgs);
+
+struct Variant {
+    const char *name;
+    int block, k, unroll;
+    KernelFn direct, partial;
+};
+
+#define FWD_VARIANT(B, K, U) \
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>}
+
+const Variant kVariants[] = {
+    FWD_VARIANT(256, 4, 4),
+    FWD_VARIANT(256, 2, 8),
+    FWD_VARIANT(256, 1, 8),
+    FWD_VARIANT(128, 2, 8),
+    FWD_VARIANT(128, 1, 8),
+    FWD_VARIANT(64, 1, 8),
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+}  // namespace
+
+int forward_variant_count() { return kNumVariants; }
+
+const char *forward_variant_name(int index)
+{
+    return (index >= 0 && index < kNumVariants) ? kVariants[index].name : nullptr;
+}
+
+int forward_default_variant(int64_t n)
+{
+    if (n >= (1 << 17)) return 0;   // b256 k4 u4
+    if (n >= (1 << 13)) return 1;   // b256 k2 u8
+    if (n >= (1 << 11)) return 4;   // b128 k1 u8
+    return 5;                       // b64 k1 u8
+}
+
+// Number of j-splits: enough workgroups to give every CU several, never a
+// split smaller than one tile.
+static int choose_splits(int n, int iblocks, int tile, int num_cu)
+{
+    const int target = 4 * num_cu;
+    const int max_splits = (n + tile - 1) / tile;
+    int s = (target + iblocks - 1) / iblocks;
+    if (s < 1) s = 1;
+    if (s > max_splits) s = max_splits;
+    return s;
+}
+
+nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m, int n,
+                         float eps2, float *a, float *p, hipStream_t stream)
+{
+    const Variant &V = kVariants[variant];
+    const int iblk = V.block * V.k;
+    const int iblocks = (n + iblk - 1) / iblk;
+    int splits = choose_splits(n, iblocks, V.block, dev.num_cu);
+    int chunk = (n + splits - 1) / splits;
+    chunk = (chunk + V.block - 1) / V.block * V.block;
+    splits = (n + chunk - 1) / chunk;
+
+    FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p};
+    if (splits == 1) {
+        if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        hipLaunchKernelGGL(V.direct, dim3(iblocks, 1), dim3(V.block), 0, stream, P);
+        return check_launch(V.name);
+    }
+    void *ws = nullptr;
+    nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
+    if (st != NBODY_OK) return st;
+    P.partial = static_cast<float4 *>(ws);
+    if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    hipLaunchKernelGGL(V.partial, dim3(iblocks, splits), dim3(V.block), 0, stream, P);
+    st = check_launch(V.name);
+    if (st != NBODY_OK) return st;
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                       P.partial, splits, n, a, p);
+    return check_launch("reduce_splits");
+}
+
+}  // namespace nbody

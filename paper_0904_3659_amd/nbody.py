@@ -1,0 +1,266 @@
+"""Python binding of libnbody.so.
+
+Argument marshalling only: tensors are checked (float32, contiguous, on the
+current HIP device, right shape), their device pointers and torch's current
+stream are handed to the C ABI (include/nbody.h), and a failing status is
+raised as :class:`NBodyError`.  Every arithmetic step runs in the HIP
+kernels of the library; there is no CPU fallback, and a missing library
+raises at first use.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+FORWARD, BACKWARD, BATCHED = 0, 1, 2
+ABI_VERSION = 1
+
+_STATUS = {
+    0: "NBODY_OK",
+    1: "NBODY_ERROR_INVALID_ARGUMENT",
+    2: "NBODY_ERROR_UNSUPPORTED_DEVICE",
+    3: "NBODY_ERROR_OUT_OF_MEMORY",
+    4: "NBODY_ERROR_LAUNCH_FAILED",
+    5: "NBODY_ERROR_INTERNAL",
+}
+
+
+class NBodyError(RuntimeError):
+    """A libnbody call returned a non-zero status."""
+
+    def __init__(self, status: int, detail: str):
+        self.status = int(status)
+        self.name = _STATUS.get(self.status, f"status {status}")
+        super().__init__(f"{self.name}: {detail}")
+
+
+_LIB = None
+_vp, _i64, _f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libnbody.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        path = os.environ.get("NBODY_LIBRARY", _build.LIBRARY)
+        if not os.path.exists(path):
+            raise NBodyError(5, f"{path} is not built; run `python -m paper_0904_3659_amd.build`")
+        L = ctypes.CDLL(path)
+        L.nbody_abi_version.restype = ctypes.c_int
+        L.nbody_status_string.restype = ctypes.c_char_p
+        L.nbody_status_string.argtypes = [ctypes.c_int]
+        L.nbody_last_error.restype = ctypes.c_char_p
+        L.nbody_forces.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp]
+        L.nbody_forces_backward.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp, _vp, _vp]
+        L.nbody_forces_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp, _vp, _vp]
+        L.nbody_axpy.argtypes = [_vp, _vp, _i64, _f32, _vp]
+        L.nbody_variant_count.argtypes = [ctypes.c_int]
+        L.nbody_variant_count.restype = ctypes.c_int
+        L.nbody_variant_name.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.nbody_variant_name.restype = ctypes.c_char_p
+        L.nbody_set_variant.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.nbody_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(_i64), _i64, _vp]
+        L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
+        L.nbody_selected_variant.restype = ctypes.c_int
+        for f in ("nbody_forces", "nbody_forces_backward", "nbody_forces_batched", "nbody_axpy",
+                  "nbody_set_variant", "nbody_autotune", "nbody_release_workspace"):
+            getattr(L, f).restype = ctypes.c_int
+        if L.nbody_abi_version() != ABI_VERSION:
+            raise NBodyError(5, f"ABI version {L.nbody_abi_version()} != {ABI_VERSION}")
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise NBodyError(status, lib().nbody_last_error().decode(errors="replace"))
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _want(t: torch.Tensor, name: str, shape, device=None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _eps2(eps2) -> float:
+    e = float(eps2)
+    if not (e >= 0.0) or e == float("inf"):
+        raise ValueError(f"eps2 must be finite and >= 0, got {eps2}")
+    return e
+
+
+# ---------------------------------------------------------------- evaluation
+
+def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential: bool = True):
+    """Eq. (gravity): (a [n,3], p [n]) in the paper's sign, j != i.
+
+    ``out`` may supply preallocated (a, p).  With ``potential=False`` the
+    potential is not stored and ``p`` is returned as None.
+    """
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    dev = x.device
+    _want(m, "m", (n,), dev)
+    if out is None:
+        a = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        p = torch.empty((n,), dtype=torch.float32, device=dev) if potential else None
+    else:
+        a, p = out
+        _want(a, "a", (n, 3), dev)
+        if p is not None:
+            _want(p, "p", (n,), dev)
+    with torch.cuda.device(dev):
+        _check(lib().nbody_forces(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p), _stream(dev)))
+    return a, p
+
+
+def forces_backward(x, m, eps2, grad_a=None, grad_p=None, *, need_grad_m: bool = True, out=None):
+    """Vector-Jacobian product of :func:`forces`: (dL/dx [n,3], dL/dm [n] or None)."""
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    dev = x.device
+    _want(m, "m", (n,), dev)
+    if grad_a is not None:
+        _want(grad_a, "grad_a", (n, 3), dev)
+    if grad_p is not None:
+        _want(grad_p, "grad_p", (n,), dev)
+    if out is None:
+        gx = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        gm = torch.empty((n,), dtype=torch.float32, device=dev) if need_grad_m else None
+    else:
+        gx, gm = out
+        _want(gx, "grad_x", (n, 3), dev)
+        if gm is not None:
+            _want(gm, "grad_m", (n,), dev)
+    with torch.cuda.device(dev):
+        _check(lib().nbody_forces_backward(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(grad_a),
+                                           _ptr(grad_p), _ptr(gx), _ptr(gm), _stream(dev)))
+    return gx, gm
+
+
+def _offsets_array(offsets) -> np.ndarray:
+    if isinstance(offsets, torch.Tensor):
+        if offsets.device.type != "cpu":
+            raise ValueError("offsets must be a host (CPU) array")
+        offsets = offsets.numpy()
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if o.ndim != 1 or o.size < 1:
+        raise ValueError("offsets must be a 1-D array of num_systems + 1 values")
+    return o
+
+
+def forces_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float, *, out=None):
+    """Eq. (gravity) on independent systems [offsets[s], offsets[s+1]).
+
+    ``offsets`` is a host array (numpy, list or CPU tensor) of int64.
+    """
+    o = _offsets_array(offsets)
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    dev = x.device
+    _want(m, "m", (n,), dev)
+    if int(o[-1]) != n:
+        raise ValueError(f"offsets[-1] = {int(o[-1])} but x holds {n} particles")
+    if out is None:
+        a = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        p = torch.empty((n,), dtype=torch.float32, device=dev)
+    else:
+        a, p = out
+        _want(a, "a", (n, 3), dev)
+        _want(p, "p", (n,), dev)
+    with torch.cuda.device(dev):
+        _check(lib().nbody_forces_batched(o.ctypes.data_as(ctypes.POINTER(_i64)), o.size - 1,
+                                          _ptr(x), _ptr(m), _eps2(eps2), _ptr(a), _ptr(p),
+                                          _stream(dev)))
+    return a, p
+
+
+def axpy_(y: torch.Tensor, xv: torch.Tensor, alpha: float) -> torch.Tensor:
+    """In place y += alpha * xv on the device (leap-frog kick and drift)."""
+    _want(y, "y", tuple(y.shape))
+    _want(xv, "x", tuple(y.shape), y.device)
+    with torch.cuda.device(y.device):
+        _check(lib().nbody_axpy(_ptr(y), _ptr(xv), y.numel(), float(alpha), _stream(y.device)))
+    return y
+
+
+# ---------------------------------------------------------------- autograd
+
+class NBodyForces(torch.autograd.Function):
+    """(a, p) = forces(x, m, eps2) with the library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, x, m, eps2):
+        a, p = forces(x, m, eps2)
+        ctx.save_for_backward(x, m)
+        ctx.eps2 = float(eps2)
+        ctx.set_materialize_grads(False)
+        return a, p
+
+    @staticmethod
+    def backward(ctx, grad_a, grad_p):
+        x, m = ctx.saved_tensors
+        if grad_a is None and grad_p is None:
+            return None, None, None
+        grad_a = None if grad_a is None else grad_a.contiguous()
+        grad_p = None if grad_p is None else grad_p.contiguous()
+        gx, gm = forces_backward(x, m, ctx.eps2, grad_a, grad_p,
+                                 need_grad_m=ctx.needs_input_grad[1])
+        return gx, gm, None
+
+
+# ---------------------------------------------------------------- variants
+
+def variant_count(kind: int) -> int:
+    return int(lib().nbody_variant_count(kind))
+
+
+def variant_names(kind: int) -> list[str]:
+    return [lib().nbody_variant_name(kind, k).decode() for k in range(variant_count(kind))]
+
+
+def set_variant(kind: int, index: int) -> None:
+    """Force a kernel variant for ``kind`` (-1 restores automatic choice)."""
+    _check(lib().nbody_set_variant(kind, index))
+
+
+def selected_variant(kind: int, n: int) -> int:
+    return int(lib().nbody_selected_variant(kind, n))
+
+
+def autotune(kind: int, sizes, device=None) -> None:
+    """Time every variant of ``kind`` at each size and keep the fastest."""
+    s = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    with torch.cuda.device(dev):
+        _check(lib().nbody_autotune(kind, s.ctypes.data_as(ctypes.POINTER(_i64)), s.size, _stream(dev)))
+
+
+def release_workspace() -> None:
+    _check(lib().nbody_release_workspace())
+
+
+from .leapfrog import leapfrog  # noqa: E402  (re-export)

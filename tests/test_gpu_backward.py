@@ -1,0 +1,130 @@
+"""GPU parity of nbody_forces_backward (the VJP of Eq. (gravity)) against the
+FP64 oracle gradient, which the CPU tests pin to finite differences."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import reference as R
+from paper_0904_3659_amd import inputs
+from tests.gpu_util import host, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# Normwise bound max_k |g - g_ref| / max_k |g_ref| and a per-row bound.
+TOL_NORM = 1e-4
+TOL_ROW = 1e-3
+
+
+@pytest.fixture(scope="module")
+def nb():
+    need_gpu()
+    from paper_0904_3659_amd import nbody
+    return nbody
+
+
+def _grad(nb, x, m, eps2, w, v, dev):
+    gx, gm = nb.forces_backward(to_dev(x, dev), to_dev(m, dev), eps2,
+                                None if w is None else to_dev(w, dev),
+                                None if v is None else to_dev(v, dev))
+    torch.cuda.synchronize()
+    return host(gx), host(gm)
+
+
+def _check(gx, gm, rx, rm, label):
+    nx = np.linalg.norm(gx - rx, axis=1)
+    ex = nx.max() / np.linalg.norm(rx, axis=1).max()
+    em = np.abs(gm - rm).max() / np.abs(rm).max()
+    big = np.linalg.norm(rx, axis=1) > 1e-2 * np.linalg.norm(rx, axis=1).max()
+    row = (nx[big] / np.linalg.norm(rx, axis=1)[big]).max() if big.any() else 0.0
+    print(f"[parity] {label} grad_x norm {ex:.2e} row {row:.2e} grad_m {em:.2e}", flush=True)
+    assert ex <= TOL_NORM and em <= TOL_NORM and row <= TOL_ROW, label
+
+
+def _system(n, seed):
+    g = np.random.default_rng(seed)
+    x = g.standard_normal((n, 3)).astype(np.float32)
+    m = g.uniform(0.1, 1.0, n).astype(np.float32)
+    w = g.standard_normal((n, 3)).astype(np.float32)
+    v = g.standard_normal(n).astype(np.float32)
+    return x, m, w, v
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 257, 1000, 3001])
+def test_random_sizes(nb, n):
+    dev = need_gpu()
+    x, m, w, v = _system(n, n)
+    gx, gm = _grad(nb, x, m, 1e-3, w, v, dev)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    _check(gx, gm, rx, rm, f"random n={n}")
+
+
+def test_single_particle(nb):
+    dev = need_gpu()
+    gx, gm = _grad(nb, np.zeros((1, 3), np.float32), np.ones(1, np.float32), 1e-4,
+                   np.ones((1, 3), np.float32), np.ones(1, np.float32), dev)
+    assert gx.tolist() == [[0.0, 0.0, 0.0]] and gm.tolist() == [0.0]
+
+
+def test_adjoint_16k_against_oracle(nb):
+    dev = need_gpu()
+    wl = inputs.adjoint_16k()
+    w, v = wl.extra["w"], wl.extra["v"]
+    gx, gm = _grad(nb, wl.x, wl.m, wl.eps2, w, v, dev)
+    rx, rm = R.forces_vjp(wl.x, wl.m, wl.eps2, w, v)
+    _check(gx, gm, rx, rm, wl.name)
+    # translation invariance and mass homogeneity of the GPU gradient
+    assert np.abs(gx.sum(0)).max() <= 1e-5 * np.linalg.norm(gx, axis=1).sum()
+    L = R.loss(wl.x, wl.m, wl.eps2, w, v)
+    assert np.sum(wl.m.astype(np.float64) * gm) == pytest.approx(L, rel=1e-4)
+
+
+def test_optional_upstreams(nb):
+    dev = need_gpu()
+    x, m, w, v = _system(500, 5)
+    for ww, vv, label in ((w, None, "w only"), (None, v, "v only")):
+        gx, gm = _grad(nb, x, m, 1e-3, ww, vv, dev)
+        rx, rm = R.forces_vjp(x, m, 1e-3, ww, vv)
+        _check(gx, gm, rx, rm, label)
+    gx, gm = _grad(nb, x, m, 1e-3, None, None, dev)
+    assert not gx.any() and not gm.any()
+
+
+def test_every_variant(nb):
+    dev = need_gpu()
+    x, m, w, v = _system(2000, 9)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    try:
+        for k in range(nb.variant_count(nb.BACKWARD)):
+            nb.set_variant(nb.BACKWARD, k)
+            gx, gm = _grad(nb, x, m, 1e-3, w, v, dev)
+            _check(gx, gm, rx, rm, nb.variant_names(nb.BACKWARD)[k])
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+
+
+def test_autograd_function(nb):
+    dev = need_gpu()
+    x, m, w, v = _system(800, 11)
+    xt = to_dev(x, dev).requires_grad_(True)
+    mt = to_dev(m, dev).requires_grad_(True)
+    a, p = nb.NBodyForces.apply(xt, mt, 1e-3)
+    loss = (a * to_dev(w, dev)).sum() + (p * to_dev(v, dev)).sum()
+    gx, gm = torch.autograd.grad(loss, (xt, mt))
+    dx, dm = nb.forces_backward(to_dev(x, dev), to_dev(m, dev), 1e-3, to_dev(w, dev), to_dev(v, dev))
+    assert torch.equal(gx, dx) and torch.equal(gm, dm)
+    # only a used: grad_p is absent and passed as NULL
+    xt.grad = None
+    a, _ = nb.NBodyForces.apply(xt, mt, 1e-3)
+    (a * to_dev(w, dev)).sum().backward()
+    rx, _ = R.forces_vjp(x, m, 1e-3, w, None)
+    gx = host(xt.grad)
+    assert np.linalg.norm(gx - rx, axis=1).max() <= TOL_NORM * np.linalg.norm(rx, axis=1).max()
+
+
+def test_deterministic(nb):
+    dev = need_gpu()
+    x, m, w, v = (to_dev(t, dev) for t in _system(3000, 13))
+    g1 = nb.forces_backward(x, m, 1e-3, w, v)
+    g2 = nb.forces_backward(x, m, 1e-3, w, v)
+    assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])

@@ -1,0 +1,194 @@
+"""GPU parity of nbody_forces (Eq. (gravity), Sec. I) against the FP64 oracle,
+called through the C ABI via the Python binding."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import reference as R
+from paper_0904_3659_amd import inputs
+from tests.gpu_util import assert_parity, errors, host, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    need_gpu()
+    from paper_0904_3659_amd import nbody
+    return nbody
+
+
+def _run(nb, x, m, eps2, dev):
+    a, p = nb.forces(to_dev(x, dev), to_dev(m, dev), eps2)
+    torch.cuda.synchronize()
+    return host(a), host(p)
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 63, 64, 65, 255, 256, 257, 1000, 1025, 5000])
+def test_small_and_ragged_sizes(nb, n):
+    dev = need_gpu()
+    g = np.random.default_rng(n)
+    x = g.standard_normal((n, 3)).astype(np.float32)
+    m = g.uniform(0.1, 1.0, n).astype(np.float32)
+    a, p = _run(nb, x, m, 1e-3, dev)
+    ar, pr = R.forces(x, m, 1e-3)
+    assert_parity(a, p, ar, pr, label=f"random n={n}")
+
+
+def test_empty_and_single(nb):
+    dev = need_gpu()
+    a, p = nb.forces(torch.zeros((0, 3), device=dev), torch.zeros((0,), device=dev), 1e-4)
+    assert a.shape == (0, 3) and p.shape == (0,)
+    a, p = _run(nb, np.array([[0.5, 0.5, 0.5]], np.float32), np.array([2.0], np.float32), 1e-4, dev)
+    assert a.tolist() == [[0.0, 0.0, 0.0]] and p.tolist() == [0.0]
+
+
+def test_two_body_exact(nb):
+    dev = need_gpu()
+    x = np.array([[0, 0, 0], [1, 0, 0]], np.float32)
+    a, p = _run(nb, x, np.array([1.0, 2.0], np.float32), 3.0, dev)
+    # s = 4: a_1 = (-m_2/8, 0, 0), p_1 = m_2/2 -- within one ulp
+    np.testing.assert_allclose(a, [[-0.25, 0, 0], [0.125, 0, 0]], rtol=1.2e-7, atol=0)
+    np.testing.assert_allclose(p, [1.0, 0.5], rtol=1.2e-7)
+
+
+def test_zero_softening(nb):
+    dev = need_gpu()
+    x = np.array([[0, 0, 0], [2, 0, 0], [0, 4, 0]], np.float32)
+    m = np.array([1, 1, 1], np.float32)
+    a, p = _run(nb, x, m, 0.0, dev)
+    ar, pr = R.forces(x, m, 0.0)
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(p))
+    assert_parity(a, p, ar, pr, tol=1e-6, label="eps2=0")
+
+
+def test_plummer_1k(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    a, p = _run(nb, w.x, w.m, w.eps2, dev)
+    ar, pr = R.forces(w.x, w.m, w.eps2)
+    assert_parity(a, p, ar, pr, label=w.name)
+
+
+@pytest.mark.parametrize("make", [inputs.plummer_64k, inputs.cube_64k])
+def test_64k_full_oracle(nb, make):
+    dev = need_gpu()
+    w = make()
+    a, p = _run(nb, w.x, w.m, w.eps2, dev)
+    ar, pr = R.forces(w.x, w.m, w.eps2)
+    assert_parity(a, p, ar, pr, label=w.name)
+
+
+def test_1m_sampled_rows(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1m_lognormal()
+    a, p = _run(nb, w.x, w.m, w.eps2, dev)
+    ar, pr = R.forces_rows(w.x, w.m, w.eps2, w.rows)
+    assert_parity(a[w.rows], p[w.rows], ar, pr, label=w.name + " (4096 rows)")
+    # momentum balance over the whole set, relative to sum m |a|
+    mom = np.abs(np.sum(w.m[:, None].astype(np.float64) * a, 0))
+    assert np.max(mom) <= 1e-4 * np.sum(w.m * np.linalg.norm(a, axis=1))
+
+
+def test_bitwise_deterministic(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    a1, p1 = nb.forces(x, m, w.eps2)
+    a2, p2 = nb.forces(x, m, w.eps2)
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_exact_mass_scaling(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    a1, p1 = nb.forces(x, m, w.eps2)
+    a2, p2 = nb.forces(x, 4.0 * m, w.eps2)
+    assert torch.equal(a2, 4.0 * a1) and torch.equal(p2, 4.0 * p1)
+
+
+def test_length_scaling(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    a1, p1 = nb.forces(x, m, w.eps2)
+    a2, p2 = nb.forces(2.0 * x, m, 4.0 * w.eps2)
+    torch.testing.assert_close(a2, a1 / 4.0, rtol=3e-7, atol=0)
+    torch.testing.assert_close(p2, p1 / 2.0, rtol=3e-7, atol=0)
+
+
+def test_permutation_equivariance(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    perm = np.random.default_rng(3).permutation(w.n)
+    a, p = _run(nb, w.x, w.m, w.eps2, dev)
+    ap, pp = _run(nb, w.x[perm], w.m[perm], w.eps2, dev)
+    e = errors(ap, pp, a[perm], p[perm])
+    assert max(e) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [700, 3000])
+def test_every_variant(nb, n):
+    dev = need_gpu()
+    g = np.random.default_rng(100 + n)
+    x = inputs.plummer_positions(n, (60, n))
+    m = g.uniform(0.1, 1.0, n).astype(np.float32)
+    ar, pr = R.forces(x, m, 1e-4)
+    try:
+        for v in range(nb.variant_count(nb.FORWARD)):
+            nb.set_variant(nb.FORWARD, v)
+            a, p = _run(nb, x, m, 1e-4, dev)
+            assert_parity(a, p, ar, pr, label=f"{nb.variant_names(nb.FORWARD)[v]} n={n}")
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
+
+
+def test_potential_optional_and_out(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    a_ref, _ = nb.forces(x, m, w.eps2)
+    a, p = nb.forces(x, m, w.eps2, potential=False)
+    assert p is None and torch.equal(a, a_ref)
+    out = (torch.full((w.n, 3), 7.0, device=dev), torch.full((w.n,), 7.0, device=dev))
+    nb.forces(x, m, w.eps2, out=out)
+    assert torch.equal(out[0], a_ref)
+
+
+def test_invalid_arguments(nb):
+    dev = need_gpu()
+    x = torch.zeros((4, 3), device=dev)
+    m = torch.ones((4,), device=dev)
+    with pytest.raises(ValueError):
+        nb.forces(x, m, -1.0)
+    with pytest.raises(ValueError):
+        nb.forces(x[:, :2], m, 1e-4)
+    with pytest.raises(ValueError):
+        nb.forces(torch.zeros((3, 4), device=dev).t(), m, 1e-4)   # not contiguous
+    with pytest.raises(TypeError):
+        nb.forces(x.double(), m, 1e-4)
+    # overlap of output and input is rejected by the library itself
+    with pytest.raises(nb.NBodyError) as ei:
+        nb.forces(x, m, 1e-4, out=(x, None))
+    assert ei.value.status == 1
+
+
+def test_fault_injection_then_recovery(nb):
+    dev = need_gpu()
+    w = inputs.plummer_1k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    good, _ = nb.forces(x, m, w.eps2)
+    for what, status in (("launch", 4), ("alloc", 3)):
+        os.environ["NBODY_FAULT"] = what
+        try:
+            with pytest.raises(nb.NBodyError) as ei:
+                nb.forces(x, m, w.eps2)   # n = 1024 uses j-splits, so it allocates
+            assert ei.value.status == status
+        finally:
+            del os.environ["NBODY_FAULT"]
+    again, _ = nb.forces(x, m, w.eps2)
+    assert torch.equal(good, again)

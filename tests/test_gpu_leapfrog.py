@@ -1,0 +1,86 @@
+"""Device-resident leap-frog (Eqs. (1)-(3), Sec. III, g = -a) and its
+checkpointed adjoint against the FP64 oracle integrator and reverse sweep."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import reference as R
+from paper_0904_3659_amd import inputs
+from tests.gpu_util import host, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    need_gpu()
+    from paper_0904_3659_amd import nbody
+    return nbody
+
+
+def _case(n, seed):
+    x = inputs.plummer_positions(n, (70, seed))
+    v = inputs.plummer_velocities(x, (70, seed, 1))
+    m = inputs.lognormal_masses(n, (70, seed, 2))
+    u = inputs.normal((n, 3), (70, seed, 3))
+    return x, v, m, u
+
+
+def _grads(nb, x, v, m, u, eps2, dt, steps, k, dev):
+    xt = to_dev(x, dev).requires_grad_(True)
+    vt = to_dev(v, dev).requires_grad_(True)
+    mt = to_dev(m, dev).requires_grad_(True)
+    xT, vT = nb.leapfrog(xt, vt, mt, eps2, dt, steps, checkpoint_every=k)
+    loss = (xT * to_dev(u, dev)).sum()
+    gx, gv, gm = torch.autograd.grad(loss, (xt, vt, mt))
+    torch.cuda.synchronize()
+    return xT.detach(), gx, gv, gm
+
+
+def test_trajectory_matches_oracle(nb):
+    dev = need_gpu()
+    x, v, m, u = _case(1024, 0)
+    xT, _, _, _ = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 8, dev)
+    rx, rv = R.leapfrog(x, v, m, 1e-4, 1e-3, 64)
+    err = np.abs(host(xT) - rx).max()
+    assert err <= 1e-5 * np.abs(rx).max()
+
+
+def test_checkpointing_is_bitwise_neutral(nb):
+    dev = need_gpu()
+    x, v, m, u = _case(2048, 1)
+    ref = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 1, dev)
+    for k in (8, 5, 64):
+        got = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, k, dev)
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), f"checkpoint_every={k}"
+
+
+def test_gradient_matches_oracle_sweep(nb):
+    dev = need_gpu()
+    x, v, m, u = _case(2048, 2)
+    _, gx, gv, gm = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 8, dev)
+    rx, rv, rm = R.leapfrog_vjp(x, v, m, 1e-4, 1e-3, 64, u)
+    for g, r, name in ((gx, rx, "x0"), (gv, rv, "v0"), (gm, rm, "m")):
+        g = host(g)
+        e = np.abs(g - r).max() / np.abs(r).max()
+        print(f"[parity] leapfrog grad {name} normwise {e:.2e}", flush=True)
+        assert e <= 1e-3, name
+
+
+def test_velocity_adjoint_input(nb):
+    # a loss on v_T as well exercises the end kick of the last step
+    dev = need_gpu()
+    x, v, m, u = _case(512, 3)
+    uv = inputs.normal(x.shape, (71, 0))
+    xt = to_dev(x, dev).requires_grad_(True)
+    vt = to_dev(v, dev).requires_grad_(True)
+    mt = to_dev(m, dev).requires_grad_(True)
+    xT, vT = nb.leapfrog(xt, vt, mt, 1e-4, 2e-3, 16, checkpoint_every=4)
+    ((xT * to_dev(u, dev)).sum() + (vT * to_dev(uv, dev)).sum()).backward()
+    rx, rv, rm = R.leapfrog_vjp(x, v, m, 1e-4, 2e-3, 16, u, uv)
+    for g, r, name in ((xt.grad, rx, "x0"), (vt.grad, rv, "v0"), (mt.grad, rm, "m")):
+        e = np.abs(host(g) - r).max() / np.abs(r).max()
+        print(f"[parity] leapfrog (x_T, v_T loss) grad {name} normwise {e:.2e}", flush=True)
+        assert e <= 1e-3, name
