@@ -76,6 +76,13 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
+ * Kernels: for 2^14 <= n <= 2^21 the default variant evaluates each
+ * unordered pair once and gives the term to both particles (the softened
+ * force is antisymmetric in the pair); it needs about 8 n^2 / 2048 bytes of
+ * library workspace (4.3 GB at n = 2^20).  Outside that range the default
+ * gathers every ordered pair per row and needs at most 16 n * splits bytes.
+ * Positions must be finite with magnitude below 1e17 (padding slots sit
+ * at +-1e18 with zero mass).
  *
  * Errors: n < 0 or n > NBODY_MAX_N, NULL x/m/a with n > 0, eps2 negative or
  * not finite, overlapping arrays -> INVALID_ARGUMENT.  n == 0 -> OK, nothing

@@ -58,6 +58,11 @@ int forward_default_variant(int64_t n);
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m,
                          int n, float eps2, float *a, float *p, hipStream_t stream);
 
+// Pair-once forward kernel (forward_sym.hip) with W waves and K rows/lane.
+nbody_status forward_sym_run(int W, int K, const char *name, const Device &dev, const float *x,
+                             const float *m, int n, float eps2, float *a, float *p,
+                             hipStream_t stream);
+
 // ---- backward (vector-Jacobian product of Eq. (gravity))
 int backward_variant_count();
 const char *backward_variant_name(int index);

@@ -28,6 +28,7 @@
 #include "common.hpp"
 
 #include <cstdio>
+#include <cstring>
 
 namespace nbody {
 namespace {
@@ -161,14 +162,19 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float4 *__rest
 
 using KernelFn = void (*)(FwdArgs);
 
+// A variant is either a gather kernel (every ordered pair, rows own all j)
+// or, when sym_w > 0, the pair-once kernel of forward_sym.hip with W waves
+// and K rows per lane.
 struct Variant {
     const char *name;
     int block, k, unroll;
     KernelFn direct, partial;
+    int sym_w, sym_k;
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0}
+#define FWD_SYM_VARIANT(W, K) {"fwd_sym_w" #W "_k" #K, 0, 0, 0, nullptr, nullptr, W, K}
 
 const Variant kVariants[] = {
     FWD_VARIANT(256, 4, 4),
@@ -177,6 +183,14 @@ const Variant kVariants[] = {
     FWD_VARIANT(128, 2, 8),
     FWD_VARIANT(128, 1, 8),
     FWD_VARIANT(64, 1, 8),
+    FWD_VARIANT(64, 2, 8),
+    FWD_VARIANT(64, 4, 4),
+    FWD_VARIANT(64, 1, 16),
+    FWD_SYM_VARIANT(4, 8),
+    FWD_SYM_VARIANT(2, 8),
+    FWD_SYM_VARIANT(1, 8),
+    FWD_SYM_VARIANT(8, 4),
+    FWD_SYM_VARIANT(2, 16),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -189,12 +203,27 @@ const char *forward_variant_name(int index)
     return (index >= 0 && index < kNumVariants) ? kVariants[index].name : nullptr;
 }
 
+static int variant_index(const char *name)
+{
+    for (int v = 0; v < kNumVariants; ++v)
+        if (std::strcmp(kVariants[v].name, name) == 0) return v;
+    return 0;
+}
+
+// Measured on MI355X: the pair-once kernel wins from a few thousand
+// particles on; its partial buffer grows as 8 n^2 / 2048 bytes, so beyond
+// 2^21 particles (17 GB) the gather kernel, which needs no workspace at all
+// at that size, takes over.
 int forward_default_variant(int64_t n)
 {
-    if (n >= (1 << 17)) return 0;   // b256 k4 u4
-    if (n >= (1 << 13)) return 1;   // b256 k2 u8
-    if (n >= (1 << 11)) return 4;   // b128 k1 u8
-    return 5;                       // b64 k1 u8
+    static const int gather_big = variant_index("fwd_b64_k1_u8");
+    static const int gather_mid = variant_index("fwd_b256_k1_u8");
+    static const int gather_small = variant_index("fwd_b64_k1_u8");
+    static const int pair_once = variant_index("fwd_sym_w8_k4");
+    if (n > (1 << 21)) return gather_big;
+    if (n >= (1 << 14)) return pair_once;
+    if (n >= (1 << 12)) return gather_mid;
+    return gather_small;
 }
 
 // Number of j-splits: enough workgroups to give every CU several, never a
@@ -213,6 +242,7 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          float eps2, float *a, float *p, hipStream_t stream)
 {
     const Variant &V = kVariants[variant];
+    if (V.sym_w) return forward_sym_run(V.sym_w, V.sym_k, V.name, dev, x, m, n, eps2, a, p, stream);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     int splits = choose_splits(n, iblocks, V.block, dev.num_cu);

@@ -192,3 +192,30 @@ def test_fault_injection_then_recovery(nb):
             del os.environ["NBODY_FAULT"]
     again, _ = nb.forces(x, m, w.eps2)
     assert torch.equal(good, again)
+
+
+@pytest.mark.parametrize("n", [2048 * 2, 4096 + 1, 2048 * 5 + 17, 2048 * 7])
+def test_pair_once_block_rings(nb, n):
+    # even and odd block counts, a ragged last block, one and many chunks
+    dev = need_gpu()
+    x = inputs.plummer_positions(n, (61, n))
+    m = inputs.lognormal_masses(n, (61, n, 1))
+    ar, pr = R.forces(x, m, 1e-4)
+    names = nb.variant_names(nb.FORWARD)
+    try:
+        for name in ("fwd_sym_w8_k4", "fwd_sym_w4_k8", "fwd_sym_w1_k8"):
+            nb.set_variant(nb.FORWARD, names.index(name))
+            a, p = _run(nb, x, m, 1e-4, dev)
+            assert_parity(a, p, ar, pr, label=f"{name} n={n}")
+            # momentum balance holds to rounding: each pair term enters twice
+            mom = np.abs(np.sum(m[:, None].astype(np.float64) * a, 0)).max()
+            assert mom <= 1e-5 * np.sum(m * np.linalg.norm(a, axis=1))
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
+
+
+def test_default_variant_choice(nb):
+    names = nb.variant_names(nb.FORWARD)
+    assert names[nb.selected_variant(nb.FORWARD, 1 << 20)].startswith("fwd_sym")
+    assert names[nb.selected_variant(nb.FORWARD, 65536)].startswith("fwd_sym")
+    assert not names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
