@@ -76,10 +76,10 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 2^14 <= n <= 2^21 the default variant evaluates each
+ * Kernels: for 2^15 <= n <= 2^21 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
- * force is antisymmetric in the pair); it needs about 8 n^2 / 2048 bytes of
- * library workspace (4.3 GB at n = 2^20).  Outside that range the default
+ * force is antisymmetric in the pair); it needs about 8 n^2 / 4096 bytes of
+ * library workspace above 2^17 particles (2.1 GB at n = 2^20).  Outside that range the default
  * gathers every ordered pair per row and needs at most 16 n * splits bytes.
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
@@ -105,6 +105,10 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
  * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
  * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
+ * Kernels: for 2^13 <= n <= 2^20 the default variant evaluates each
+ * unordered pair once (the x-gradient term is antisymmetric in the pair)
+ * with about 8 n^2 / 1024 bytes of workspace; otherwise every ordered pair
+ * is gathered per row.
  */
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
                                    const float *grad_a, const float *grad_p,
@@ -116,9 +120,12 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
  * itself.  `offsets` is a HOST array of num_systems + 1 int64 values with
  * offsets[0] == 0, non-decreasing; the total is offsets[num_systems].
  * Empty systems are allowed.  The library builds a work plan from the
- * offsets (cost-ordered list of (system, i-tile) units), caches it keyed by
- * the offsets' content, uploads it to library workspace and runs one
- * persistent launch.  Per-system results equal nbody_forces on that system
+ * offsets (a cost-ordered list of units: (system, 256-particle block) for
+ * the default pair-once variant, (system, i-tile) for gather variants),
+ * caches it keyed by the offsets' content, uploads it to library memory and
+ * runs one persistent launch (plus one launch that adds the pair-once
+ * partial sums; about 16 (1 + M_s/2) N_s bytes of workspace per system of
+ * N_s particles in M_s blocks).  Per-system results equal nbody_forces on that system
  * up to float32 summation order, and are bitwise independent of the other
  * systems' contents.
  *

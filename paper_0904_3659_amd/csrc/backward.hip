@@ -17,6 +17,8 @@
 // the running sums (two-level accumulation).  No atomics.
 #include "common.hpp"
 
+#include <cstring>
+
 namespace nbody {
 namespace {
 
@@ -228,22 +230,333 @@ __global__ __launch_bounds__(256) void backward_reduce_kernel(const float4 *__re
     if (gm) gm[i] = s.w;
 }
 
+// ---------------------------------------------------------------------------
+// Pair-once adjoint.  With d = x_k - x_j, c_kj = m_j w_k - m_k w_j and
+// b_kj = m_j v_k + m_k v_j, the x-gradient term
+//     F(k, j) = r^3 c_kj - r^3 (3 r^2 (c_kj . d) + b_kj) d
+// satisfies F(j, k) = -F(k, j) (c and d flip sign, b and c.d do not), so one
+// evaluation serves both rows: dL/dx_k += F, dL/dx_j -= F.  The mass terms
+//     dL/dm_k += r v_j - r^3 (w_j . d),   dL/dm_j += r v_k + r^3 (w_k . d)
+// share r, r^3 and the two dot products.  The block/ring decomposition, LDS
+// slot read-modify-writes and partial slots are those of the pair-once
+// forward kernel (forward_sym.hip); tiles hold two float4 per particle.
+
+struct SymBwdArgs {
+    const float *x;
+    const float *m;
+    const float *ga;
+    const float *gp;
+    int n;
+    float eps2;
+    int M;
+    int C;
+    float4 *partial;  // [C + M/2][n]: (dL/dx, dL/dm)
+};
+
+__device__ __forceinline__ int bwd_ring_len(int I, int M)
+{
+    return (M - 1) / 2 + (((M & 1) == 0 && I < M / 2) ? 1 : 0);
+}
+
+// One unordered pair: adds F and the k mass term to tk; returns the j-side
+// contributions (-F, j mass term) through jx..jm.
+__device__ __forceinline__ void adj_pair_once(const float4 &xk, const float4 &wk, const float4 &q,
+                                              const float4 &wq, float eps2, float4 &tk, float &jx,
+                                              float &jy, float &jz, float &jm)
+{
+    const float dx = xk.x - q.x;
+    const float dy = xk.y - q.y;
+    const float dz = xk.z - q.z;
+    float s = __builtin_fmaf(dx, dx, eps2);
+    s = __builtin_fmaf(dy, dy, s);
+    s = __builtin_fmaf(dz, dz, s);
+    const float r = __builtin_amdgcn_rsqf(s);
+    const float r2 = r * r;
+    const float r3 = r * r2;
+    float wkd = wk.x * dx;
+    wkd = __builtin_fmaf(wk.y, dy, wkd);
+    wkd = __builtin_fmaf(wk.z, dz, wkd);
+    float wjd = wq.x * dx;
+    wjd = __builtin_fmaf(wq.y, dy, wjd);
+    wjd = __builtin_fmaf(wq.z, dz, wjd);
+    const float cd = __builtin_fmaf(q.w, wkd, -xk.w * wjd);
+    const float b = __builtin_fmaf(xk.w, wq.w, q.w * wk.w);
+    // F = r^3 (c - t d) with t = 3 r^2 (c . d) + b
+    const float t = __builtin_fmaf(3.0f * r2, cd, b);
+    const float cx = __builtin_fmaf(q.w, wk.x, -xk.w * wq.x);
+    const float cy = __builtin_fmaf(q.w, wk.y, -xk.w * wq.y);
+    const float cz = __builtin_fmaf(q.w, wk.z, -xk.w * wq.z);
+    const float Fx = r3 * __builtin_fmaf(-t, dx, cx);
+    const float Fy = r3 * __builtin_fmaf(-t, dy, cy);
+    const float Fz = r3 * __builtin_fmaf(-t, dz, cz);
+    tk.x += Fx;
+    tk.y += Fy;
+    tk.z += Fz;
+    tk.w = __builtin_fmaf(r, wq.w, tk.w);
+    tk.w = __builtin_fmaf(-r3, wjd, tk.w);
+    jx = -Fx;
+    jy = -Fy;
+    jz = -Fz;
+    jm = __builtin_fmaf(r3, wkd, r * wk.w);
+}
+
+// The k-side alone, with the pair removed when `skip` holds (diagonal tiles).
+__device__ __forceinline__ void adj_row_term(const float4 &xk, const float4 &wk, const float4 &q,
+                                             const float4 &wq, float eps2, bool skip, float4 &tk)
+{
+    const float dx = xk.x - q.x;
+    const float dy = xk.y - q.y;
+    const float dz = xk.z - q.z;
+    float s = __builtin_fmaf(dx, dx, eps2);
+    s = __builtin_fmaf(dy, dy, s);
+    s = __builtin_fmaf(dz, dz, s);
+    const float r = skip ? 0.0f : __builtin_amdgcn_rsqf(s);
+    const float r2 = r * r;
+    const float r3 = r * r2;
+    float wkd = wk.x * dx;
+    wkd = __builtin_fmaf(wk.y, dy, wkd);
+    wkd = __builtin_fmaf(wk.z, dz, wkd);
+    float wjd = wq.x * dx;
+    wjd = __builtin_fmaf(wq.y, dy, wjd);
+    wjd = __builtin_fmaf(wq.z, dz, wjd);
+    const float cd = __builtin_fmaf(q.w, wkd, -xk.w * wjd);
+    const float b = __builtin_fmaf(xk.w, wq.w, q.w * wk.w);
+    const float t = __builtin_fmaf(3.0f * r2, cd, b);
+    tk.x = __builtin_fmaf(r3, __builtin_fmaf(-t, dx, __builtin_fmaf(q.w, wk.x, -xk.w * wq.x)), tk.x);
+    tk.y = __builtin_fmaf(r3, __builtin_fmaf(-t, dy, __builtin_fmaf(q.w, wk.y, -xk.w * wq.y)), tk.y);
+    tk.z = __builtin_fmaf(r3, __builtin_fmaf(-t, dz, __builtin_fmaf(q.w, wk.z, -xk.w * wq.z)), tk.z);
+    tk.w = __builtin_fmaf(r, wq.w, tk.w);
+    tk.w = __builtin_fmaf(-r3, wjd, tk.w);
+}
+
+constexpr float kBwdPadRow = 1e18f;
+constexpr float kBwdPadCol = -1e18f;
+
+template <int W, int K>
+__global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
+{
+    constexpr int PB = W * 64 * K;
+    constexpr int TPB = PB / 64;
+    __shared__ float4 tile_xm[64];
+    __shared__ float4 tile_wv[64];
+    __shared__ float4 jacc[W][64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int n = A.n;
+    const int M = A.M, C = A.C;
+    const int I = blockIdx.x / C;
+    const int c = blockIdx.x - I * C;
+    const float eps2 = A.eps2;
+
+    float4 xk[K], wk[K], acc[K];
+    int kk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = I * PB + wv * 64 * K + k * 64 + lane;
+        kk[k] = i;
+        if (i < n) {
+            xk[k] = make_float4(A.x[3 * i], A.x[3 * i + 1], A.x[3 * i + 2], A.m[i]);
+            wk[k] = make_float4(A.ga ? A.ga[3 * i] : 0.f, A.ga ? A.ga[3 * i + 1] : 0.f,
+                                A.ga ? A.ga[3 * i + 2] : 0.f, A.gp ? A.gp[i] : 0.f);
+        } else {
+            xk[k] = make_float4(kBwdPadRow, kBwdPadRow, kBwdPadRow, 0.f);
+            wk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int t = tid; t < W * 64; t += W * 64) (&jacc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    // The block's tile sequence is its TPB diagonal tiles followed by its
+    // ring tiles (delta-major); chunk c takes an equal share of it.
+    const int U = TPB + bwd_ring_len(I, M) * TPB;
+    const int u0 = (int)((long long)U * c / C);
+    const int u1 = (int)((long long)U * (c + 1) / C);
+
+    for (int u = u0; u < u1; ++u) {
+        int jbase, delta;
+        if (u < TPB) {
+            delta = 0;
+            jbase = I * PB + u * 64;
+        } else {
+            const int q = u - TPB;
+            delta = 1 + q / TPB;
+            const int t = q - (delta - 1) * TPB;
+            int J = I + delta;
+            if (J >= M) J -= M;
+            jbase = J * PB + t * 64;
+        }
+        if (jbase >= n) continue;
+
+        __syncthreads();
+        if (tid < 64) {
+            const int j = jbase + tid;
+            if (j < n) {
+                tile_xm[tid] = make_float4(A.x[3 * j], A.x[3 * j + 1], A.x[3 * j + 2], A.m[j]);
+                tile_wv[tid] = make_float4(A.ga ? A.ga[3 * j] : 0.f, A.ga ? A.ga[3 * j + 1] : 0.f,
+                                           A.ga ? A.ga[3 * j + 2] : 0.f, A.gp ? A.gp[j] : 0.f);
+            } else {
+                tile_xm[tid] = make_float4(kBwdPadCol, kBwdPadCol, kBwdPadCol, 0.f);
+                tile_wv[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();
+
+        float4 tk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) tk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+        if (delta == 0) {
+            for (int s = 0; s < 64; ++s) {
+                const float4 q = tile_xm[s];
+                const float4 wq = tile_wv[s];
+                const int j = jbase + s;
+#pragma unroll
+                for (int k = 0; k < K; ++k) adj_row_term(xk[k], wk[k], q, wq, eps2, j == kk[k], tk[k]);
+            }
+        } else {
+            float4 *slot = &jacc[wv][0];
+            float4 q = tile_xm[lane];
+            float4 wq = tile_wv[lane];
+            for (int s = 0; s < 64; ++s) {
+                const int jj = (lane + s) & 63;
+                // keep this step's slot read after the previous step's write
+                __asm__ volatile("" ::: "memory");
+                float4 ja = slot[jj];
+                const float4 qn = tile_xm[(jj + 1) & 63];
+                const float4 wqn = tile_wv[(jj + 1) & 63];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    float jx, jy, jz, jm;
+                    adj_pair_once(xk[k], wk[k], q, wq, eps2, tk[k], jx, jy, jz, jm);
+                    ja.x += jx;
+                    ja.y += jy;
+                    ja.z += jz;
+                    ja.w += jm;
+                }
+                slot[jj] = ja;
+                q = qn;
+                wq = wqn;
+            }
+            __asm__ volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            acc[k].x += tk[k].x;
+            acc[k].y += tk[k].y;
+            acc[k].z += tk[k].z;
+            acc[k].w += tk[k].w;
+        }
+        if (delta != 0) {
+            __syncthreads();
+            if (tid < 64) {
+                float4 sum = jacc[0][tid];
+                jacc[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int w2 = 1; w2 < W; ++w2) {
+                    const float4 v = jacc[w2][tid];
+                    sum.x += v.x;
+                    sum.y += v.y;
+                    sum.z += v.z;
+                    sum.w += v.w;
+                    jacc[w2][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                const int j = jbase + tid;
+                if (j < n) A.partial[(size_t)(C + delta - 1) * n + j] = sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (kk[k] < n) A.partial[(size_t)c * n + kk[k]] = acc[k];
+}
+
+template <int PB>
+__global__ __launch_bounds__(256) void backward_sym_reduce_kernel(const float4 *__restrict__ partial,
+                                                                  int n, int M, int C, float *gx,
+                                                                  float *gm)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int J = j / PB;
+    const int H = (M - 1) / 2 + (((M & 1) == 0 && J >= M / 2) ? 1 : 0);
+    float4 s = partial[j];
+    for (int k = 1; k < C + H; ++k) {
+        const float4 q = partial[(size_t)k * n + j];
+        s.x += q.x;
+        s.y += q.y;
+        s.z += q.z;
+        s.w += q.w;
+    }
+    gx[3 * j + 0] = s.x;
+    gx[3 * j + 1] = s.y;
+    gx[3 * j + 2] = s.z;
+    if (gm) gm[j] = s.w;
+}
+
+// OCC divides the chunk count (as in the pair-once forward kernel).
+template <int W, int K, int OCC>
+nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
+                              int n, float eps2, const float *ga, const float *gp, float *gx,
+                              float *gm, hipStream_t stream)
+{
+    constexpr int PB = W * 64 * K;
+    const int M = (n + PB - 1) / PB;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_sym_kernel<W, K>,
+                                                                W * 64, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (per_cu < 1) per_cu = 1;
+    int C = per_cu * dev.num_cu / (M * OCC);
+    if (C < 1) C = 1;
+    const int max_c = (M / 2 + 1) * (PB / 64);
+    if (C > max_c) C = max_c;
+    const int slots = C + M / 2;
+    void *ws = nullptr;
+    nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)slots * n, &ws);
+    if (st != NBODY_OK) return st;
+    SymBwdArgs A{x, m, ga, gp, n, eps2, M, C, static_cast<float4 *>(ws)};
+    if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    hipLaunchKernelGGL((backward_sym_kernel<W, K>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    st = check_launch(name);
+    if (st != NBODY_OK) return st;
+    hipLaunchKernelGGL((backward_sym_reduce_kernel<PB>), dim3((n + 255) / 256), dim3(256), 0,
+                       stream, A.partial, n, M, C, gx, gm);
+    return check_launch("backward_sym_reduce");
+}
+
 using KernelFn = void (*)(BwdArgs);
 
+using SymRunFn = nbody_status (*)(const char *, const Device &, const float *, const float *,
+                                  int, float, const float *, const float *, float *, float *,
+                                  hipStream_t);
+
+// A gather variant (rows own all j) or, with sym set, a pair-once variant.
 struct Variant {
     const char *name;
     int block, k, unroll;
     KernelFn direct, partial;
+    SymRunFn sym;
 };
 
 #define BWD_VARIANT(B, K, U) \
-    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>}
+    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr}
+#define BWD_SYM_VARIANT(W, K, O) {"bwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, O>}
 
 const Variant kVariants[] = {
     BWD_VARIANT(256, 2, 4),
     BWD_VARIANT(256, 1, 8),
     BWD_VARIANT(128, 1, 8),
     BWD_VARIANT(64, 1, 4),
+    BWD_VARIANT(64, 1, 8),
+    BWD_VARIANT(64, 2, 4),
+    BWD_SYM_VARIANT(8, 2, 1),
+    BWD_SYM_VARIANT(8, 2, 2),
+    BWD_SYM_VARIANT(4, 2, 1),
+    BWD_SYM_VARIANT(4, 2, 2),
+    BWD_SYM_VARIANT(8, 4, 1),
+    BWD_SYM_VARIANT(16, 2, 1),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -256,12 +569,27 @@ const char *backward_variant_name(int index)
     return (index >= 0 && index < kNumVariants) ? kVariants[index].name : nullptr;
 }
 
+static int variant_index(const char *name)
+{
+    for (int v = 0; v < kNumVariants; ++v)
+        if (std::strcmp(kVariants[v].name, name) == 0) return v;
+    return 0;
+}
+
+// Measured on MI355X: the pair-once adjoint wins from 2^13 particles on; its
+// partial buffer grows as 8 n^2 / 1024 bytes, so above 2^20 particles the
+// gather kernel takes over.
 int backward_default_variant(int64_t n)
 {
-    if (n >= (1 << 15)) return 0;
-    if (n >= (1 << 12)) return 1;
-    if (n >= (1 << 10)) return 2;
-    return 3;
+    static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
+    static const int pair_once_small = variant_index("bwd_sym_w4_k2_o1");
+    static const int gather = variant_index("bwd_b256_k1_u8");
+    static const int gather_small = variant_index("bwd_b128_k1_u8");
+    if (n > (1 << 20)) return gather;
+    if (n >= (1 << 15)) return pair_once;
+    if (n >= (1 << 13)) return pair_once_small;
+    if (n >= (1 << 11)) return gather;
+    return gather_small;
 }
 
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m, int n,
@@ -269,6 +597,7 @@ nbody_status backward_run(int variant, const Device &dev, const float *x, const 
                           hipStream_t stream)
 {
     const Variant &V = kVariants[variant];
+    if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     const int target = 4 * dev.num_cu;

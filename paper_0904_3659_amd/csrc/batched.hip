@@ -10,6 +10,11 @@
 //   workgroups in a snake order (g, 2G-1-g, 2G+g, ...), which balances the
 //   static schedule without atomics or counters.
 //
+// Pair-once variants (bat_sym_*): a unit is (system s, block I) and runs the
+// pair-once block evaluation of pair_once.hpp on that system alone (one
+// chunk per block); its partial slots live in a per-plan region of library
+// workspace, and a second launch adds each particle's slots in fixed order.
+//
 // Kernel: a grid of exactly as many workgroups as the device holds at once;
 // workgroup g walks its units, staging each system's j-range through LDS
 // in BLOCK-particle tiles with the same masked/unmasked split, register
@@ -17,6 +22,7 @@
 // never read one another's particles, so a system's result does not depend
 // on the rest of the batch.
 #include "common.hpp"
+#include "pair_once.hpp"
 
 #include <algorithm>
 #include <cstring>
@@ -26,10 +32,6 @@
 
 namespace nbody {
 namespace {
-
-struct Unit {
-    int i_begin, i_end, j_begin, j_end;
-};
 
 struct BatArgs {
     const int4 *units;
@@ -103,20 +105,93 @@ __global__ __launch_bounds__(BLOCK) void batched_kernel(BatArgs P)
     }
 }
 
+// ---- pair-once units: {system base, system size, block I, partial offset}
+struct BatSymArgs {
+    const int4 *units;
+    int num_units;
+    const float *x;
+    const float *m;
+    float eps2;
+    float4 *partial;
+};
+
+template <int W, int K>
+__global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
+{
+    constexpr int PB = W * 64 * K;
+    __shared__ float4 tile[64];
+    __shared__ float4 jacc[W][64];
+    const int G = gridDim.x;
+    const int g = blockIdx.x;
+    for (int round = 0;; ++round) {
+        const int idx = (round & 1) ? round * G + (G - 1 - g) : round * G + g;
+        if (idx >= A.num_units) break;
+        const int4 u = A.units[idx];
+        const int ns = u.y;
+        const int M = (ns + PB - 1) / PB;
+        pair_once_block<W, K>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
+                              A.partial + u.w, tile, jacc);
+    }
+}
+
+// a, p of block I of system s = its slots (i-side, then the ring slots the
+// block received), added in slot order.  One workgroup per unit.
+template <int PB>
+__global__ __launch_bounds__(256) void batched_sym_reduce_kernel(const int4 *__restrict__ units,
+                                                                 const float4 *__restrict__ partial,
+                                                                 float *a, float *p)
+{
+    const int4 u = units[blockIdx.x];
+    const int ns = u.y;
+    const int M = (ns + PB - 1) / PB;
+    const int slots = 1 + ring_in(u.z, M);
+    const float4 *P = partial + u.w;
+    const int lo = u.z * PB;
+    const int hi = min(ns, lo + PB);
+    for (int j = lo + (int)threadIdx.x; j < hi; j += 256) {
+        float4 s = P[j];
+        for (int k = 1; k < slots; ++k) {
+            const float4 q = P[(size_t)k * ns + j];
+            s.x += q.x;
+            s.y += q.y;
+            s.z += q.z;
+            s.w += q.w;
+        }
+        const size_t g = (size_t)u.x + j;
+        a[3 * g + 0] = s.x;
+        a[3 * g + 1] = s.y;
+        a[3 * g + 2] = s.z;
+        if (p) p[g] = s.w;
+    }
+}
+
 using KernelFn = void (*)(BatArgs);
+using SymKernelFn = void (*)(BatSymArgs);
+using SymReduceFn = void (*)(const int4 *, const float4 *, float *, float *);
 
 struct Variant {
     const char *name;
     int block, unroll;
     KernelFn fn;
+    int sym_pb;          // particles per block of the pair-once variant (0: gather)
+    SymKernelFn sym_fn;
+    SymReduceFn sym_reduce;
+    int sym_threads;
 };
 
-#define BAT_VARIANT(B, U) {"bat_b" #B "_u" #U, B, U, batched_kernel<B, U>}
+#define BAT_VARIANT(B, U) {"bat_b" #B "_u" #U, B, U, batched_kernel<B, U>, 0, nullptr, nullptr, 0}
+#define BAT_SYM_VARIANT(W, K) \
+    {"bat_sym_w" #W "_k" #K, 0, 0, nullptr, W * 64 * K, batched_sym_kernel<W, K>, \
+     batched_sym_reduce_kernel<W * 64 * K>, W * 64}
 
 const Variant kVariants[] = {
     BAT_VARIANT(64, 8),
     BAT_VARIANT(128, 8),
     BAT_VARIANT(256, 8),
+    BAT_SYM_VARIANT(1, 4),
+    BAT_SYM_VARIANT(1, 8),
+    BAT_SYM_VARIANT(2, 4),
+    BAT_SYM_VARIANT(4, 4),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -128,6 +203,7 @@ struct Plan {
     std::vector<int64_t> offsets;  // exact key
     int num_units = 0;
     int grid = 0;
+    size_t partial_elems = 0;      // float4 slots (pair-once variants)
     int4 *d_units = nullptr;
     ~Plan()
     {
@@ -164,31 +240,48 @@ nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
 
     struct Item {
         int64_t cost;
-        int64_t order;
-        Unit u;
+        int4 u;
     };
     std::vector<Item> items;
-    int64_t order = 0;
-    for (int64_t s = 0; s < num_systems; ++s) {
-        const int64_t lo = offsets[s], hi = offsets[s + 1];
-        const int64_t ns = hi - lo;
-        if (ns <= 0) continue;
-        const int64_t padded_j = (ns + V.block - 1) / V.block * V.block;
-        for (int64_t t = lo; t < hi; t += V.block) {
-            Unit u{(int)t, (int)std::min<int64_t>(hi, t + V.block), (int)lo, (int)hi};
-            items.push_back(Item{padded_j, order++, u});
+    if (V.sym_pb == 0) {
+        for (int64_t s = 0; s < num_systems; ++s) {
+            const int64_t lo = offsets[s], hi = offsets[s + 1];
+            const int64_t ns = hi - lo;
+            if (ns <= 0) continue;
+            const int64_t padded_j = (ns + V.block - 1) / V.block * V.block;
+            for (int64_t t = lo; t < hi; t += V.block)
+                items.push_back(Item{padded_j, make_int4((int)t, (int)std::min<int64_t>(hi, t + V.block),
+                                                         (int)lo, (int)hi)});
         }
+    } else {
+        // unit (system, block I); cost = the block's 64-particle tiles
+        size_t poff = 0;
+        for (int64_t s = 0; s < num_systems; ++s) {
+            const int64_t lo = offsets[s], ns = offsets[s + 1] - offsets[s];
+            if (ns <= 0) continue;
+            const int M = (int)((ns + V.sym_pb - 1) / V.sym_pb);
+            for (int I = 0; I < M; ++I) {
+                const int64_t tiles = (int64_t)(1 + ring_len(I, M)) * (V.sym_pb / 64);
+                items.push_back(Item{tiles, make_int4((int)lo, (int)ns, I, (int)poff)});
+            }
+            poff += (size_t)(1 + M / 2) * (size_t)ns;
+        }
+        plan->partial_elems = poff;
+        if (poff > (size_t)INT32_MAX)
+            return fail(NBODY_ERROR_INVALID_ARGUMENT,
+                        "ensemble too large for the pair-once batched variant (%zu partial slots)", poff);
     }
+    // largest first; ties keep system order
     std::stable_sort(items.begin(), items.end(),
                      [](const Item &p, const Item &q) { return p.cost > q.cost; });
     std::vector<int4> host(items.size());
-    for (size_t k = 0; k < items.size(); ++k)
-        host[k] = make_int4(items[k].u.i_begin, items[k].u.i_end, items[k].u.j_begin,
-                            items[k].u.j_end);
+    for (size_t k = 0; k < items.size(); ++k) host[k] = items[k].u;
     plan->num_units = (int)host.size();
 
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.fn, V.block, 0);
+    hipError_t e = V.sym_pb
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.sym_fn, V.sym_threads, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.fn, V.block, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     int64_t grid = (int64_t)per_cu * dev.num_cu;
@@ -212,6 +305,13 @@ nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
     return NBODY_OK;
 }
 
+int variant_index(const char *name)
+{
+    for (int v = 0; v < kNumVariants; ++v)
+        if (std::strcmp(kVariants[v].name, name) == 0) return v;
+    return 0;
+}
+
 }  // namespace
 
 int batched_variant_count() { return kNumVariants; }
@@ -221,11 +321,14 @@ const char *batched_variant_name(int index)
     return (index >= 0 && index < kNumVariants) ? kVariants[index].name : nullptr;
 }
 
+// Measured on MI355X (4,096 Plummer systems of 8..2048 particles): the
+// pair-once variant with 256-particle blocks is fastest; very small systems
+// gain nothing from pairing and take the gather variant.
 int batched_default_variant(int64_t mean_n)
 {
-    if (mean_n >= 4096) return 2;
-    if (mean_n >= 512) return 1;
-    return 0;
+    static const int pair_once = variant_index("bat_sym_w1_k4");
+    static const int gather = variant_index("bat_b64_u8");
+    return mean_n >= 128 ? pair_once : gather;
 }
 
 void release_batched_plans()
@@ -243,6 +346,19 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
     if (st != NBODY_OK) return st;
     if (plan->num_units == 0) return NBODY_OK;
     const Variant &V = kVariants[variant];
+    if (V.sym_pb) {
+        void *ws = nullptr;
+        st = workspace(dev, stream, sizeof(float4) * plan->partial_elems, &ws);
+        if (st != NBODY_OK) return st;
+        BatSymArgs S{plan->d_units, plan->num_units, x, m, eps2, static_cast<float4 *>(ws)};
+        if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        hipLaunchKernelGGL(V.sym_fn, dim3(plan->grid), dim3(V.sym_threads), 0, stream, S);
+        st = check_launch(V.name);
+        if (st != NBODY_OK) return st;
+        hipLaunchKernelGGL(V.sym_reduce, dim3(plan->num_units), dim3(256), 0, stream,
+                           (const int4 *)plan->d_units, (const float4 *)S.partial, a, p);
+        return check_launch("batched_sym_reduce");
+    }
     BatArgs P{plan->d_units, plan->num_units, x, m, eps2, a, p};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
     hipLaunchKernelGGL(V.fn, dim3(plan->grid), dim3(V.block), 0, stream, P);

@@ -59,8 +59,8 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          int n, float eps2, float *a, float *p, hipStream_t stream);
 
 // Pair-once forward kernel (forward_sym.hip) with W waves and K rows/lane.
-nbody_status forward_sym_run(int W, int K, const char *name, const Device &dev, const float *x,
-                             const float *m, int n, float eps2, float *a, float *p,
+nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
+                             const float *x, const float *m, int n, float eps2, float *a, float *p,
                              hipStream_t stream);
 
 // ---- backward (vector-Jacobian product of Eq. (gravity))

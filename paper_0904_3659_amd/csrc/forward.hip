@@ -169,12 +169,12 @@ struct Variant {
     const char *name;
     int block, k, unroll;
     KernelFn direct, partial;
-    int sym_w, sym_k;
+    int sym_w, sym_k, sym_occ;
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0}
-#define FWD_SYM_VARIANT(W, K) {"fwd_sym_w" #W "_k" #K, 0, 0, 0, nullptr, nullptr, W, K}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O}
 
 const Variant kVariants[] = {
     FWD_VARIANT(256, 4, 4),
@@ -186,11 +186,12 @@ const Variant kVariants[] = {
     FWD_VARIANT(64, 2, 8),
     FWD_VARIANT(64, 4, 4),
     FWD_VARIANT(64, 1, 16),
-    FWD_SYM_VARIANT(4, 8),
-    FWD_SYM_VARIANT(2, 8),
-    FWD_SYM_VARIANT(1, 8),
-    FWD_SYM_VARIANT(8, 4),
-    FWD_SYM_VARIANT(2, 16),
+    FWD_SYM_VARIANT(8, 4, 1),
+    FWD_SYM_VARIANT(8, 4, 2),
+    FWD_SYM_VARIANT(4, 8, 1),
+    FWD_SYM_VARIANT(4, 4, 1),
+    FWD_SYM_VARIANT(2, 8, 1),
+    FWD_SYM_VARIANT(16, 4, 1),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -210,18 +211,20 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once kernel wins from a few thousand
-// particles on; its partial buffer grows as 8 n^2 / 2048 bytes, so beyond
-// 2^21 particles (17 GB) the gather kernel, which needs no workspace at all
-// at that size, takes over.
+// Measured on MI355X: the pair-once kernel wins from about 2^15 particles
+// on (W = 16 waves above 2^17); its partial buffer grows as 8 n^2 / P bytes
+// (P = 2048 or 4096 particles per block), so beyond 2^21 particles the
+// gather kernel, which needs no workspace at that size, takes over.
 int forward_default_variant(int64_t n)
 {
     static const int gather_big = variant_index("fwd_b64_k1_u8");
     static const int gather_mid = variant_index("fwd_b256_k1_u8");
-    static const int gather_small = variant_index("fwd_b64_k1_u8");
-    static const int pair_once = variant_index("fwd_sym_w8_k4");
+    static const int gather_small = variant_index("fwd_b128_k1_u8");
+    static const int pair_once_mid = variant_index("fwd_sym_w4_k4_o1");
+    static const int pair_once_big = variant_index("fwd_sym_w16_k4_o1");
     if (n > (1 << 21)) return gather_big;
-    if (n >= (1 << 14)) return pair_once;
+    if (n >= (1 << 17)) return pair_once_big;
+    if (n >= (1 << 15)) return pair_once_mid;
     if (n >= (1 << 12)) return gather_mid;
     return gather_small;
 }
@@ -242,7 +245,8 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          float eps2, float *a, float *p, hipStream_t stream)
 {
     const Variant &V = kVariants[variant];
-    if (V.sym_w) return forward_sym_run(V.sym_w, V.sym_k, V.name, dev, x, m, n, eps2, a, p, stream);
+    if (V.sym_w)
+        return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     int splits = choose_splits(n, iblocks, V.block, dev.num_cu);

@@ -128,3 +128,22 @@ def test_deterministic(nb):
     g1 = nb.forces_backward(x, m, 1e-3, w, v)
     g2 = nb.forces_backward(x, m, 1e-3, w, v)
     assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
+
+
+@pytest.mark.parametrize("n", [2048 * 2 + 5, 2048 * 3, 4096 * 5 + 100])
+def test_pair_once_block_rings(nb, n):
+    dev = need_gpu()
+    x, m, w, v = _system(n, 40 + n)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    names = nb.variant_names(nb.BACKWARD)
+    try:
+        for name in [nm for nm in names if nm.startswith("bwd_sym")]:
+            nb.set_variant(nb.BACKWARD, names.index(name))
+            gx, gm = _grad(nb, x, m, 1e-3, w, v, dev)
+            _check(gx, gm, rx, rm, f"{name} n={n}")
+            # optional upstreams through the pair-once path as well
+            gx1, gm1 = _grad(nb, x, m, 1e-3, None, v, dev)
+            rx1, rm1 = R.forces_vjp(x, m, 1e-3, None, v)
+            _check(gx1, gm1, rx1, rm1, f"{name} n={n} v only")
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)

@@ -203,7 +203,7 @@ def test_pair_once_block_rings(nb, n):
     ar, pr = R.forces(x, m, 1e-4)
     names = nb.variant_names(nb.FORWARD)
     try:
-        for name in ("fwd_sym_w8_k4", "fwd_sym_w4_k8", "fwd_sym_w1_k8"):
+        for name in [nm for nm in names if nm.startswith("fwd_sym")]:
             nb.set_variant(nb.FORWARD, names.index(name))
             a, p = _run(nb, x, m, 1e-4, dev)
             assert_parity(a, p, ar, pr, label=f"{name} n={n}")
@@ -218,4 +218,5 @@ def test_default_variant_choice(nb):
     names = nb.variant_names(nb.FORWARD)
     assert names[nb.selected_variant(nb.FORWARD, 1 << 20)].startswith("fwd_sym")
     assert names[nb.selected_variant(nb.FORWARD, 65536)].startswith("fwd_sym")
+    assert not names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
