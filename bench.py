@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-interactions/s & % FP32 VALU peak (38 flop/pair): fwd, adjoint, batched"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_plummer_n1048576_traffic.txt")
 FORWARD_SOURCES = [os.path.join(ROOT, "paper_0904_3659_amd", "csrc", f)
-                   for f in ("forward.hip", "common.hpp")]
+                   for f in ("forward.hip", "forward_sym.hip", "pair_once.hpp", "common.hpp")]
 
 
 def log(msg: str) -> None:
@@ -61,21 +61,24 @@ def read_traffic():
         return None
 
 
-def timed_calls(fn, reps: int, torch):
-    """Run fn() reps times; per-call HIP-event durations (ms) on the current
-    stream (where the library launches) and the wall time of the whole loop."""
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
+def timed_calls(fn, reps: int, torch, nb):
+    """Run fn() reps times between two synchronisations.
+
+    Returns (wall seconds of the loop, mean pair-kernel ms, mean whole-call
+    kernel ms).  The kernel figures come from the library's own HIP events,
+    recorded on the stream it launches on (torch's current stream) around
+    its pair kernel and after its last kernel."""
     torch.cuda.synchronize()
+    nb.profile_enable(True)
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
+    for _ in range(reps):
         fn()
-        b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return [a.elapsed_time(b) for a, b in evs], wall
+    main_ms, total_ms, calls = nb.profile_read()
+    nb.profile_enable(False)
+    assert calls == reps, (calls, reps)
+    return wall, main_ms, total_ms
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -147,11 +150,10 @@ def main() -> int:
         fwd()
     torch.cuda.synchronize()
     log(f"forward timed x{args.steps}")
-    per_call, wall = timed_calls(fwd, args.steps, torch)
+    wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb)
     pairs = metrics.pairs(w.n)
     ms_step = wall * 1e3 / args.steps
     value = pairs / (wall / args.steps)
-    kern_ms = float(np.mean(per_call))
     achieved = pairs * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3) / 1e12
     peak = metrics.MI355X_FP32_VECTOR_TFLOPS
     traffic = read_traffic()
@@ -176,9 +178,28 @@ def main() -> int:
         "frac_fp32_peak_38flop": value * metrics.FLOP_PER_PAIR / (peak * 1e12),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": variant, "kernel_ms": kern_ms,
+                     "kernel": variant, "kernel_ms": kern_ms, "call_kernels_ms": call_ms,
                      "flop_per_pair": metrics.FLOP_PER_PAIR},
     }
+
+    # ---------------------------------------------------------- other sizes
+    if not args.only_forward:
+        sizes = {}
+        for make in (inputs.plummer_1k, inputs.plummer_64k, inputs.cube_64k):
+            ws = make()
+            xs, ms_ = torch.from_numpy(ws.x).to(dev), torch.from_numpy(ws.m).to(dev)
+            f = lambda: nb.forces(xs, ms_, ws.eps2)
+            for _ in range(3):
+                f()
+            reps = 50 if ws.n <= 4096 else 20
+            wl, km, cm = timed_calls(f, reps, torch, nb)
+            pr = metrics.pairs(ws.n)
+            sizes[ws.name] = {"ms_per_call": wl * 1e3 / reps, "kernels_ms": cm, "pair_kernel_ms": km,
+                              "pairs_per_s": pr / (wl / reps),
+                              "frac_fp32_peak_38flop_kernel": metrics.frac_of_fp32_peak(pr / (km * 1e-3)),
+                              "variant": nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, ws.n)]}
+            log(f"forward {ws.name}: {wl * 1e3 / reps:.4f} ms/call")
+        out["forward_other_sizes"] = sizes
 
     if not args.only_forward:
         # ------------------------------------------------------ adjoint, 16k
@@ -193,18 +214,41 @@ def main() -> int:
         bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
         for _ in range(3):
             bwd()
-        per, wall_a = timed_calls(bwd, 20, torch)
+        wall_a, ka, ca = timed_calls(bwd, 50, torch, nb)
         pa = metrics.pairs(wa.n)
-        ka = float(np.median(per))
         out["adjoint"] = {
-            "workload": wa.name, "pairs_per_s": pa / (wall_a / 20), "kernel_ms": ka,
-            "pairs_per_s_kernel": pa / (ka * 1e-3),
-            "frac_fp32_peak_38flop": pa / (ka * 1e-3) * 38 / (peak * 1e12),
-            "frac_fp32_peak_own_flop": pa / (ka * 1e-3) * 68 / (peak * 1e12),
+            "workload": wa.name, "ms_per_call": wall_a * 1e3 / 50, "pairs_per_s": pa / (wall_a / 50),
+            "pair_kernel_ms": ka, "kernels_ms": ca,
+            "pairs_per_s_kernels": pa / (ca * 1e-3),
+            "frac_fp32_peak_38flop": pa / (ca * 1e-3) * 38 / (peak * 1e12),
+            "frac_fp32_peak_own_flop": pa / (ca * 1e-3) * 68 / (peak * 1e12),
             "own_flop_per_pair": 68,
             "variant": nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)],
         }
-        log(f"adjoint {ka:.3f} ms")
+        log(f"adjoint {ca:.3f} ms (kernels)")
+
+        # ------------------------------------------- leap-frog with checkpoints
+        log("leap-frog leg")
+        x0 = torch.from_numpy(wa.x).to(dev).requires_grad_(True)
+        v0 = torch.from_numpy(wa.extra["v0"]).to(dev).requires_grad_(True)
+        mm = torch.from_numpy(wa.m).to(dev).requires_grad_(True)
+        u = torch.from_numpy(wa.extra["u"]).to(dev)
+
+        def lf():
+            xT, _ = nb.leapfrog(x0, v0, mm, wa.eps2, 1e-3, 64, checkpoint_every=8)
+            torch.autograd.grad((xT * u).sum(), (x0, v0, mm))
+
+        lf()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lf()
+        torch.cuda.synchronize()
+        lf_s = time.perf_counter() - t0
+        # 65 + 8 recomputed force evaluations, 64 VJPs
+        out["leapfrog_grad"] = {"workload": wa.name + "_64steps_dt1e-3_ckpt8", "seconds": lf_s,
+                                "force_evals": 73, "vjp_evals": 64,
+                                "pairs_per_s": (73 + 64) * pa / lf_s}
+        log(f"leap-frog gradient {lf_s * 1e3:.1f} ms")
 
         # ------------------------------------------------------ batched
         log("batched leg")
@@ -220,7 +264,7 @@ def main() -> int:
         bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
         for _ in range(2):
             bat()
-        per_b, wall_b = timed_calls(bat, 10, torch)
+        wall_b, kbm, kb = timed_calls(bat, 10, torch, nb)
         views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
                  for lo, hi in zip(ens.offsets[:-1], ens.offsets[1:]) if hi > lo]
 
@@ -229,12 +273,16 @@ def main() -> int:
                 nb.forces(xs, ms, ens.eps2, out=(as_, ps))
 
         plain()
-        _, wall_plain = timed_calls(plain, 1, torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        wall_plain = time.perf_counter() - t0
         pb_pairs = metrics.pairs_ensemble(ens.sizes())
-        kb = float(np.median(per_b))
         out["batched"] = {
             "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
-            "pairs": pb_pairs, "persistent_ms": kb, "pairs_per_s": pb_pairs / (kb * 1e-3),
+            "pairs": pb_pairs, "persistent_ms": kb, "persistent_pair_kernel_ms": kbm,
+            "ms_per_call": wall_b * 1e3 / 10, "pairs_per_s": pb_pairs / (kb * 1e-3),
             "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
             "plain_launches_ms": wall_plain * 1e3,
             "speedup_vs_plain": wall_plain * 1e3 / kb,

@@ -180,6 +180,27 @@ int nbody_selected_variant(int kind, int64_t n);
 /* Free every cached workspace of every device and stream (synchronises). */
 nbody_status nbody_release_workspace(void);
 
+/* -------------------------------------------------------------- profiling */
+
+/*
+ * Kernel timing of the library's own launches.  While enabled (on != 0),
+ * every successful nbody_forces / nbody_forces_backward /
+ * nbody_forces_batched call of the calling thread records three HIP events
+ * on its stream: before its pair kernel, after its pair kernel, and after
+ * its last kernel (the partial-sum reduction, if any).  The last 256 calls
+ * are kept.  Enabling or disabling clears the record.  Costs three event
+ * records per call; off by default.
+ */
+nbody_status nbody_profile_enable(int on);
+
+/*
+ * Wait for the recorded calls of this thread and return the mean duration
+ * of the pair kernel (main_ms) and of the whole call's kernels (total_ms)
+ * over them, and their number (calls; 0 leaves the means at 0).  Clears the
+ * record.  NULL outputs are skipped.
+ */
+nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls);
+
 #ifdef __cplusplus
 }
 #endif

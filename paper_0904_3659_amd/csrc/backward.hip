@@ -518,7 +518,9 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     if (st != NBODY_OK) return st;
     SymBwdArgs A{x, m, ga, gp, n, eps2, M, C, static_cast<float4 *>(ws)};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    prof_mark(stream, 0);
     hipLaunchKernelGGL((backward_sym_kernel<W, K>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
     hipLaunchKernelGGL((backward_sym_reduce_kernel<PB>), dim3((n + 255) / 256), dim3(256), 0,
@@ -611,7 +613,9 @@ nbody_status backward_run(int variant, const Device &dev, const float *x, const 
     BwdArgs P{x, m, ga, gp, n, eps2, chunk, nullptr, gx, gm};
     if (splits == 1) {
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
         hipLaunchKernelGGL(V.direct, dim3(iblocks, 1), dim3(V.block), 0, stream, P);
+        prof_mark(stream, 1);
         return check_launch(V.name);
     }
     void *ws = nullptr;
@@ -619,7 +623,9 @@ nbody_status backward_run(int variant, const Device &dev, const float *x, const 
     if (st != NBODY_OK) return st;
     P.partial = static_cast<float4 *>(ws);
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    prof_mark(stream, 0);
     hipLaunchKernelGGL(V.partial, dim3(iblocks, splits), dim3(V.block), 0, stream, P);
+    prof_mark(stream, 1);
     st = check_launch(V.name);
     if (st != NBODY_OK) return st;
     hipLaunchKernelGGL(backward_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,

@@ -352,7 +352,9 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
         if (st != NBODY_OK) return st;
         BatSymArgs S{plan->d_units, plan->num_units, x, m, eps2, static_cast<float4 *>(ws)};
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
         hipLaunchKernelGGL(V.sym_fn, dim3(plan->grid), dim3(V.sym_threads), 0, stream, S);
+        prof_mark(stream, 1);
         st = check_launch(V.name);
         if (st != NBODY_OK) return st;
         hipLaunchKernelGGL(V.sym_reduce, dim3(plan->num_units), dim3(256), 0, stream,
@@ -361,7 +363,9 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
     }
     BatArgs P{plan->d_units, plan->num_units, x, m, eps2, a, p};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    prof_mark(stream, 0);
     hipLaunchKernelGGL(V.fn, dim3(plan->grid), dim3(V.block), 0, stream, P);
+    prof_mark(stream, 1);
     return check_launch(V.name);
 }
 

@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -140,6 +141,56 @@ nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void
     }
     *ptr = b.ptr;
     return NBODY_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+
+namespace {
+constexpr int kProfSlots = 256;
+std::atomic<bool> g_prof_on{false};
+struct ProfState {
+    int device = -1;
+    std::vector<hipEvent_t> ev;  // kProfSlots x 3
+    int next = 0;
+    int count = 0;
+    bool pending = false;  // mark 0 recorded for the current call
+    ~ProfState()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+thread_local ProfState t_prof;
+
+bool prof_ready()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (t_prof.device == dev && !t_prof.ev.empty()) return true;
+    for (hipEvent_t e : t_prof.ev) (void)hipEventDestroy(e);
+    t_prof.ev.assign(3 * kProfSlots, nullptr);
+    for (auto &e : t_prof.ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            t_prof.ev.clear();
+            return false;
+        }
+    t_prof.device = dev;
+    t_prof.next = 0;
+    t_prof.count = 0;
+    return true;
+}
+}  // namespace
+
+void prof_mark(hipStream_t stream, int which)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed) || !prof_ready()) return;
+    if (which == 0) t_prof.pending = true;
+    if (!t_prof.pending) return;  // a call that launched no pair kernel is not recorded
+    (void)hipEventRecord(t_prof.ev[3 * t_prof.next + which], stream);
+    if (which == 2) {
+        t_prof.pending = false;
+        t_prof.next = (t_prof.next + 1) % kProfSlots;
+        if (t_prof.count < kProfSlots) ++t_prof.count;
+    }
 }
 
 // ---------------------------------------------------------------- variants
@@ -331,8 +382,10 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
     Device dev;
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
-    return forward_run(select_variant(NBODY_KIND_FORWARD, n), dev, x, m, (int)n, eps2, a, p,
-                       (hipStream_t)stream);
+    st = forward_run(select_variant(NBODY_KIND_FORWARD, n), dev, x, m, (int)n, eps2, a, p,
+                     (hipStream_t)stream);
+    if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
+    return st;
 }
 
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
@@ -358,8 +411,10 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
     Device dev;
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
-    return backward_run(select_variant(NBODY_KIND_BACKWARD, n), dev, x, m, (int)n, eps2, grad_a,
-                        grad_p, grad_x, grad_m, (hipStream_t)stream);
+    st = backward_run(select_variant(NBODY_KIND_BACKWARD, n), dev, x, m, (int)n, eps2, grad_a,
+                      grad_p, grad_x, grad_m, (hipStream_t)stream);
+    if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
+    return st;
 }
 
 nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, const float *x,
@@ -388,8 +443,10 @@ nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, c
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     const int64_t mean_n = num_systems > 0 ? n / num_systems : 0;
-    return batched_run(select_variant(NBODY_KIND_BATCHED, mean_n), dev, offsets, num_systems, x,
-                       m, eps2, a, p, (hipStream_t)stream);
+    st = batched_run(select_variant(NBODY_KIND_BATCHED, mean_n), dev, offsets, num_systems, x,
+                     m, eps2, a, p, (hipStream_t)stream);
+    if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
+    return st;
 }
 
 nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, void *stream)
@@ -447,6 +504,41 @@ nbody_status nbody_release_workspace(void)
     }
     g_ws.clear();
     return st;
+}
+
+nbody_status nbody_profile_enable(int on)
+{
+    clear_error();
+    g_prof_on.store(on != 0);
+    t_prof.next = 0;
+    t_prof.count = 0;
+    t_prof.pending = false;
+    return NBODY_OK;
+}
+
+nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls)
+{
+    clear_error();
+    double sm = 0.0, st = 0.0;
+    const int cnt = t_prof.count;
+    for (int k = 0; k < cnt; ++k) {
+        const int slot = (t_prof.next - cnt + k + kProfSlots) % kProfSlots;
+        hipEvent_t *e = &t_prof.ev[3 * slot];
+        hipError_t err = hipEventSynchronize(e[2]);
+        if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize(profile)");
+        float a = 0.f, b = 0.f;
+        err = hipEventElapsedTime(&a, e[0], e[1]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&b, e[0], e[2]);
+        if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime(profile)");
+        sm += a;
+        st += b;
+    }
+    if (main_ms) *main_ms = cnt ? sm / cnt : 0.0;
+    if (total_ms) *total_ms = cnt ? st / cnt : 0.0;
+    if (calls) *calls = cnt;
+    t_prof.next = 0;
+    t_prof.count = 0;
+    return NBODY_OK;
 }
 
 nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void *stream)

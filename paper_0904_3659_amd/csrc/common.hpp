@@ -45,6 +45,10 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes);
 // Launch status of the last kernel launch on this thread.
 nbody_status check_launch(const char *what);
 
+// Profiling marks (no-ops unless nbody_profile_enable(1)): 0 before the
+// pair kernel, 1 after it, 2 after the call's last kernel (commits).
+void prof_mark(hipStream_t stream, int which);
+
 // Forced variant (>= 0) for a kind, or -1 for automatic choice.
 int forced_variant(int kind);
 // Tuned variant for (kind, n) from the tuning table, or -1.

@@ -257,7 +257,9 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
     FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p};
     if (splits == 1) {
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
         hipLaunchKernelGGL(V.direct, dim3(iblocks, 1), dim3(V.block), 0, stream, P);
+        prof_mark(stream, 1);
         return check_launch(V.name);
     }
     void *ws = nullptr;
@@ -265,7 +267,9 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
     if (st != NBODY_OK) return st;
     P.partial = static_cast<float4 *>(ws);
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    prof_mark(stream, 0);
     hipLaunchKernelGGL(V.partial, dim3(iblocks, splits), dim3(V.block), 0, stream, P);
+    prof_mark(stream, 1);
     st = check_launch(V.name);
     if (st != NBODY_OK) return st;
     hipLaunchKernelGGL(reduce_splits_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,

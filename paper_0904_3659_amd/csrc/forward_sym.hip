@@ -77,7 +77,9 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     if (st != NBODY_OK) return st;
     SymArgs A{x, m, n, eps2, M, C, static_cast<float4 *>(ws)};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    prof_mark(stream, 0);
     hipLaunchKernelGGL((forward_sym_kernel<W, K>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
     hipLaunchKernelGGL((forward_sym_reduce_kernel<PB>), dim3((n + 255) / 256), dim3(256), 0, stream,

@@ -66,10 +66,15 @@ def lib() -> ctypes.CDLL:
         L.nbody_variant_name.restype = ctypes.c_char_p
         L.nbody_set_variant.argtypes = [ctypes.c_int, ctypes.c_int]
         L.nbody_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(_i64), _i64, _vp]
+        L.nbody_profile_enable.argtypes = [ctypes.c_int]
+        L.nbody_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int)]
         L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
         L.nbody_selected_variant.restype = ctypes.c_int
         for f in ("nbody_forces", "nbody_forces_backward", "nbody_forces_batched", "nbody_axpy",
-                  "nbody_set_variant", "nbody_autotune", "nbody_release_workspace"):
+                  "nbody_set_variant", "nbody_autotune", "nbody_release_workspace",
+                  "nbody_profile_enable", "nbody_profile_read"):
             getattr(L, f).restype = ctypes.c_int
         if L.nbody_abi_version() != ABI_VERSION:
             raise NBodyError(5, f"ABI version {L.nbody_abi_version()} != {ABI_VERSION}")
@@ -261,6 +266,18 @@ def autotune(kind: int, sizes, device=None) -> None:
 
 def release_workspace() -> None:
     _check(lib().nbody_release_workspace())
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around the library's own kernels (this thread)."""
+    _check(lib().nbody_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(mean pair-kernel ms, mean whole-call ms, calls) since the last read."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    _check(lib().nbody_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 from .leapfrog import leapfrog  # noqa: E402  (re-export)

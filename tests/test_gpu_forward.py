@@ -220,3 +220,20 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 65536)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
+
+
+def test_profile_hook(nb):
+    dev = need_gpu()
+    w = inputs.plummer_64k()
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    nb.profile_enable(True)
+    try:
+        for _ in range(3):
+            nb.forces(x, m, w.eps2)
+        main_ms, total_ms, calls = nb.profile_read()
+        assert calls == 3 and 0.0 < main_ms <= total_ms
+        assert nb.profile_read()[2] == 0          # reading clears the record
+        nb.forces(torch.zeros((0, 3), device=dev), torch.zeros((0,), device=dev), 1e-4)
+        assert nb.profile_read()[2] == 0          # n = 0 launches nothing
+    finally:
+        nb.profile_enable(False)
