@@ -120,7 +120,7 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
  * itself.  `offsets` is a HOST array of num_systems + 1 int64 values with
  * offsets[0] == 0, non-decreasing; the total is offsets[num_systems].
  * Empty systems are allowed.  The library builds a work plan from the
- * offsets (a cost-ordered list of units: (system, 256-particle block) for
+ * offsets (a cost-ordered list of units: (system, 192-particle block) for
  * the default pair-once variant, (system, i-tile) for gather variants),
  * caches it keyed by the offsets' content, uploads it to library memory and
  * runs one persistent launch (plus one launch that adds the pair-once

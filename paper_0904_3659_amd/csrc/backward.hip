@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256) void backward_reduce_kernel(const float4 *__re
 //     dL/dm_k += r v_j - r^3 (w_j . d),   dL/dm_j += r v_k + r^3 (w_k . d)
 // share r, r^3 and the two dot products.  The block/ring decomposition, LDS
 // slot read-modify-writes and partial slots are those of the pair-once
-// forward kernel (forward_sym.hip); tiles hold two float4 per particle.
+// forward kernel (pair_once.hpp), diagonal tiles included; tiles hold two
+// float4 per particle.
 
 struct SymBwdArgs {
     const float *x;
@@ -332,6 +333,59 @@ __device__ __forceinline__ void adj_row_term(const float4 &xk, const float4 &wk,
 constexpr float kBwdPadRow = 1e18f;
 constexpr float kBwdPadCol = -1e18f;
 
+__device__ __forceinline__ void load_xw(const SymBwdArgs &A, int j, float4 &xm, float4 &wv)
+{
+    if (j < A.n) {
+        xm = make_float4(A.x[3 * j], A.x[3 * j + 1], A.x[3 * j + 2], A.m[j]);
+        wv = make_float4(A.ga ? A.ga[3 * j] : 0.f, A.ga ? A.ga[3 * j + 1] : 0.f,
+                         A.ga ? A.ga[3 * j + 2] : 0.f, A.gp ? A.gp[j] : 0.f);
+    } else {
+        xm = make_float4(kBwdPadCol, kBwdPadCol, kBwdPadCol, 0.f);
+        wv = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// The 64 steps of one tile for one wave (lane l meets tile particle
+// (l + s) mod 64 at step s).  Ring tiles: every row tile pair-once.
+// Diagonal tile t: row tile a = a0 + k pair-once if a < t, masked ordered
+// pairs if a == t, nothing if a > t (met on diagonal tile a).
+template <int K, bool DIAG>
+__device__ __forceinline__ void adj_tile_steps(const float4 (&xk)[K], const float4 (&wk)[K],
+                                               const int (&kk)[K], const float4 *tile_xm,
+                                               const float4 *tile_wv, float4 *slot, int lane,
+                                               int a0, int t, int jbase, float eps2,
+                                               float4 (&tk)[K])
+{
+    const bool any_once = !DIAG || a0 < t;
+    float4 q = tile_xm[lane];
+    float4 wq = tile_wv[lane];
+    for (int s = 0; s < 64; ++s) {
+        const int jj = (lane + s) & 63;
+        // keep this step's slot read after the previous step's write
+        __asm__ volatile("" ::: "memory");
+        float4 ja = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (any_once) ja = slot[jj];
+        const float4 qn = tile_xm[(jj + 1) & 63];
+        const float4 wqn = tile_wv[(jj + 1) & 63];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!DIAG || a0 + k < t) {
+                float jx, jy, jz, jm;
+                adj_pair_once(xk[k], wk[k], q, wq, eps2, tk[k], jx, jy, jz, jm);
+                ja.x += jx;
+                ja.y += jy;
+                ja.z += jz;
+                ja.w += jm;
+            } else if (a0 + k == t) {
+                adj_row_term(xk[k], wk[k], q, wq, eps2, jbase + jj == kk[k], tk[k]);
+            }
+        }
+        if (any_once) slot[jj] = ja;
+        q = qn;
+        wq = wqn;
+    }
+}
+
 template <int W, int K>
 __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 {
@@ -357,9 +411,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         const int i = I * PB + wv * 64 * K + k * 64 + lane;
         kk[k] = i;
         if (i < n) {
-            xk[k] = make_float4(A.x[3 * i], A.x[3 * i + 1], A.x[3 * i + 2], A.m[i]);
-            wk[k] = make_float4(A.ga ? A.ga[3 * i] : 0.f, A.ga ? A.ga[3 * i + 1] : 0.f,
-                                A.ga ? A.ga[3 * i + 2] : 0.f, A.gp ? A.gp[i] : 0.f);
+            load_xw(A, i, xk[k], wk[k]);
         } else {
             xk[k] = make_float4(kBwdPadRow, kBwdPadRow, kBwdPadRow, 0.f);
             wk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -368,79 +420,51 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
     }
     for (int t = tid; t < W * 64; t += W * 64) (&jacc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 
-    // The block's tile sequence is its TPB diagonal tiles followed by its
-    // ring tiles (delta-major); chunk c takes an equal share of it.
+    // this chunk's share of the block's tiles (diagonal first, then the ring
+    // delta-major); all-padding tiles are skipped (uniform)
     const int U = TPB + bwd_ring_len(I, M) * TPB;
     const int u0 = (int)((long long)U * c / C);
     const int u1 = (int)((long long)U * (c + 1) / C);
-
-    for (int u = u0; u < u1; ++u) {
-        int jbase, delta;
+    auto base_of = [&](int u, int &delta) {
         if (u < TPB) {
             delta = 0;
-            jbase = I * PB + u * 64;
-        } else {
-            const int q = u - TPB;
-            delta = 1 + q / TPB;
-            const int t = q - (delta - 1) * TPB;
-            int J = I + delta;
-            if (J >= M) J -= M;
-            jbase = J * PB + t * 64;
+            return I * PB + u * 64;
         }
-        if (jbase >= n) continue;
+        const int q = u - TPB;
+        delta = 1 + q / TPB;
+        int J = I + delta;
+        if (J >= M) J -= M;
+        return J * PB + (q - (delta - 1) * TPB) * 64;
+    };
+    int u = u0, delta = 0, jbase = 0;
+    for (; u < u1; ++u)
+        if ((jbase = base_of(u, delta)) < n) break;
+    float4 nxm = make_float4(0.f, 0.f, 0.f, 0.f), nwv = nxm;
+    if (u < u1 && tid < 64) load_xw(A, jbase + tid, nxm, nwv);
 
+    while (u < u1) {
         __syncthreads();
         if (tid < 64) {
-            const int j = jbase + tid;
-            if (j < n) {
-                tile_xm[tid] = make_float4(A.x[3 * j], A.x[3 * j + 1], A.x[3 * j + 2], A.m[j]);
-                tile_wv[tid] = make_float4(A.ga ? A.ga[3 * j] : 0.f, A.ga ? A.ga[3 * j + 1] : 0.f,
-                                           A.ga ? A.ga[3 * j + 2] : 0.f, A.gp ? A.gp[j] : 0.f);
-            } else {
-                tile_xm[tid] = make_float4(kBwdPadCol, kBwdPadCol, kBwdPadCol, 0.f);
-                tile_wv[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            tile_xm[tid] = nxm;
+            tile_wv[tid] = nwv;
         }
         __syncthreads();
+        const int cur_u = u, cur_delta = delta, cur_base = jbase;
+        for (++u; u < u1; ++u)
+            if ((jbase = base_of(u, delta)) < n) break;
+        if (u < u1 && tid < 64) load_xw(A, jbase + tid, nxm, nwv);
 
         float4 tk[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) tk[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-
-        if (delta == 0) {
-            for (int s = 0; s < 64; ++s) {
-                const float4 q = tile_xm[s];
-                const float4 wq = tile_wv[s];
-                const int j = jbase + s;
-#pragma unroll
-                for (int k = 0; k < K; ++k) adj_row_term(xk[k], wk[k], q, wq, eps2, j == kk[k], tk[k]);
-            }
-        } else {
-            float4 *slot = &jacc[wv][0];
-            float4 q = tile_xm[lane];
-            float4 wq = tile_wv[lane];
-            for (int s = 0; s < 64; ++s) {
-                const int jj = (lane + s) & 63;
-                // keep this step's slot read after the previous step's write
-                __asm__ volatile("" ::: "memory");
-                float4 ja = slot[jj];
-                const float4 qn = tile_xm[(jj + 1) & 63];
-                const float4 wqn = tile_wv[(jj + 1) & 63];
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    float jx, jy, jz, jm;
-                    adj_pair_once(xk[k], wk[k], q, wq, eps2, tk[k], jx, jy, jz, jm);
-                    ja.x += jx;
-                    ja.y += jy;
-                    ja.z += jz;
-                    ja.w += jm;
-                }
-                slot[jj] = ja;
-                q = qn;
-                wq = wqn;
-            }
-            __asm__ volatile("" ::: "memory");
-        }
+        float4 *slot = &jacc[wv][0];
+        const bool diag = (cur_delta == 0);
+        if (!diag)
+            adj_tile_steps<K, false>(xk, wk, kk, tile_xm, tile_wv, slot, lane, 0, 0, 0, eps2, tk);
+        else
+            adj_tile_steps<K, true>(xk, wk, kk, tile_xm, tile_wv, slot, lane, wv * K, cur_u,
+                                    cur_base, eps2, tk);
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             acc[k].x += tk[k].x;
@@ -448,8 +472,8 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
             acc[k].z += tk[k].z;
             acc[k].w += tk[k].w;
         }
-        if (delta != 0) {
-            __syncthreads();
+        __syncthreads();  // every wave's j-side slots are complete
+        if (!diag) {
             if (tid < 64) {
                 float4 sum = jacc[0][tid];
                 jacc[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -462,9 +486,31 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                     sum.w += v.w;
                     jacc[w2][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                const int j = jbase + tid;
-                if (j < n) A.partial[(size_t)(C + delta - 1) * n + j] = sum;
+                const int j = cur_base + tid;
+                if (j < n) A.partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
             }
+        } else if (wv == cur_u / K) {
+            // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K)
+            float4 sum = jacc[0][lane];
+            jacc[0][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int w2 = 1; w2 < W; ++w2) {
+                const float4 v = jacc[w2][lane];
+                sum.x += v.x;
+                sum.y += v.y;
+                sum.z += v.z;
+                sum.w += v.w;
+                jacc[w2][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            const int kt = cur_u - wv * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k == kt) {
+                    acc[k].x += sum.x;
+                    acc[k].y += sum.y;
+                    acc[k].z += sum.z;
+                    acc[k].w += sum.w;
+                }
         }
     }
 #pragma unroll

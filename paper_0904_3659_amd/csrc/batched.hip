@@ -189,9 +189,11 @@ const Variant kVariants[] = {
     BAT_VARIANT(128, 8),
     BAT_VARIANT(256, 8),
     BAT_SYM_VARIANT(1, 4),
+    BAT_SYM_VARIANT(1, 2),
+    BAT_SYM_VARIANT(1, 3),
+    BAT_SYM_VARIANT(2, 2),
     BAT_SYM_VARIANT(1, 8),
     BAT_SYM_VARIANT(2, 4),
-    BAT_SYM_VARIANT(4, 4),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -322,11 +324,11 @@ const char *batched_variant_name(int index)
 }
 
 // Measured on MI355X (4,096 Plummer systems of 8..2048 particles): the
-// pair-once variant with 256-particle blocks is fastest; very small systems
+// pair-once variant with 192-particle blocks is fastest; very small systems
 // gain nothing from pairing and take the gather variant.
 int batched_default_variant(int64_t mean_n)
 {
-    static const int pair_once = variant_index("bat_sym_w1_k4");
+    static const int pair_once = variant_index("bat_sym_w1_k3");
     static const int gather = variant_index("bat_b64_u8");
     return mean_n >= 128 ? pair_once : gather;
 }

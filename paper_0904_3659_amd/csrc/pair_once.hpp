@@ -12,8 +12,9 @@
 //   A system of n particles is cut into M blocks of P = W*64*K.  The caller
 //   (one workgroup) owns block I, chunk c of C: it keeps block I in VGPRs
 //   (K rows per lane, W waves) and meets
-//     - its own block (the diagonal) as ordered pairs, i-side only, j == i
-//       removed by index, and
+//     - its own block (the diagonal), pair-once between different 64-row
+//       tiles and as ordered pairs (j == i removed by index) within a tile,
+//       and
 //     - the blocks J = I + delta (mod M) for delta = 1..H_I (the ring), with
 //       H_I = (M-1)/2, plus delta = M/2 when M is even and I < M/2,
 //   so every unordered pair of distinct blocks is met exactly once.  The
@@ -60,10 +61,131 @@ __host__ __device__ __forceinline__ int ring_in(int J, int M)
     return (M - 1) / 2 + (((M & 1) == 0 && J >= M / 2) ? 1 : 0);
 }
 
+// Tile u of block I's sequence: the TPB diagonal tiles (delta 0), then the
+// ring tiles delta-major.  Returns the first particle index of the tile.
+template <int PB>
+__device__ __forceinline__ int tile_base(int u, int I, int M, int &delta)
+{
+    constexpr int TPB = PB / 64;
+    if (u < TPB) {
+        delta = 0;
+        return I * PB + u * 64;
+    }
+    const int q = u - TPB;
+    delta = 1 + q / TPB;
+    int J = I + delta;
+    if (J >= M) J -= M;
+    return J * PB + (q - (delta - 1) * TPB) * 64;
+}
+
+__device__ __forceinline__ float4 load_particle(const float *__restrict__ x,
+                                                const float *__restrict__ m, int j, int n)
+{
+    return (j < n) ? make_float4(x[3 * j], x[3 * j + 1], x[3 * j + 2], m[j])
+                   : make_float4(kPadCol, kPadCol, kPadCol, 0.0f);
+}
+
+// One pair met once: i-side added to (tx, ty, tz, tp); j-side added to
+// (gx, gy, gz, gp), or stored there when FIRST (the first row of a step).
+template <bool FIRST>
+__device__ __forceinline__ void pair_once_term(float xi, float yi, float zi, float mi, float4 q,
+                                               float eps2, float &tx, float &ty, float &tz,
+                                               float &tp, float &gx, float &gy, float &gz,
+                                               float &gp)
+{
+    const float dx = xi - q.x;
+    const float dy = yi - q.y;
+    const float dz = zi - q.z;
+    float s2 = __builtin_fmaf(dx, dx, eps2);
+    s2 = __builtin_fmaf(dy, dy, s2);
+    s2 = __builtin_fmaf(dz, dz, s2);
+    const float r = __builtin_amdgcn_rsqf(s2);
+    const float r3 = r * (r * r);
+    // i-side: + m_j r^3 d, + m_j r
+    const float f = q.w * r3;
+    tp = __builtin_fmaf(q.w, r, tp);
+    tx = __builtin_fmaf(f, dx, tx);
+    ty = __builtin_fmaf(f, dy, ty);
+    tz = __builtin_fmaf(f, dz, tz);
+    // j-side: - m_i r^3 d, + m_i r
+    const float g = mi * r3;
+    if (FIRST) {
+        gx = -g * dx;
+        gy = -g * dy;
+        gz = -g * dz;
+        gp = mi * r;
+    } else {
+        gx = __builtin_fmaf(-g, dx, gx);
+        gy = __builtin_fmaf(-g, dy, gy);
+        gz = __builtin_fmaf(-g, dz, gz);
+        gp = __builtin_fmaf(mi, r, gp);
+    }
+}
+
+// The 64 steps of one tile for one wave.  Lane l meets tile particle
+// (l + s) mod 64 at step s.  Ring tiles (DIAG false): every row tile meets
+// the tile pair-once.  Diagonal tile t (DIAG true): row tile a = a0 + k
+// meets it pair-once if a < t, as masked ordered pairs if a == t, not at all
+// if a > t.  j-side sums go to this wave's LDS slots (read-modify-write).
+template <int K, bool DIAG>
+__device__ __forceinline__ void tile_steps(const float (&xi)[K], const float (&yi)[K],
+                                           const float (&zi)[K], const float (&mi)[K],
+                                           const int (&ii)[K], const float4 *tile, float4 *slot,
+                                           int lane, int a0, int t, int jbase, float eps2,
+                                           float (&tx)[K], float (&ty)[K], float (&tz)[K],
+                                           float (&tp)[K])
+{
+    const bool any_once = !DIAG || a0 < t;
+    float4 q = tile[lane];
+    for (int s = 0; s < 64; ++s) {
+        const int jj = (lane + s) & 63;
+        // Compiler-only barrier: this step's slot read stays after the
+        // previous step's slot write (another lane may have written it).
+        __asm__ volatile("" ::: "memory");
+        float4 ja = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (any_once) ja = slot[jj];
+        const float4 qn = tile[(jj + 1) & 63];  // next step's particle (read-only tile)
+        float gx = 0.f, gy = 0.f, gz = 0.f, gp = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!DIAG) {
+                if (k == 0)
+                    pair_once_term<true>(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k],
+                                         tp[k], gx, gy, gz, gp);
+                else
+                    pair_once_term<false>(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k],
+                                          tp[k], gx, gy, gz, gp);
+            } else if (a0 + k < t) {
+                pair_once_term<false>(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k],
+                                      tp[k], gx, gy, gz, gp);
+            } else if (a0 + k == t) {
+                pair_term_masked(xi[k], yi[k], zi[k], q, eps2, jbase + jj == ii[k], tx[k], ty[k],
+                                 tz[k], tp[k]);
+            }
+        }
+        if (any_once) {
+            ja.x += gx;
+            ja.y += gy;
+            ja.z += gz;
+            ja.w += gp;
+            slot[jj] = ja;
+        }
+        q = qn;
+    }
+}
+
 // One workgroup of W*64 lanes evaluates chunk c of block I.  x, m and
 // partial are the system's own arrays (offsets already applied).  tile and
 // jacc are the workgroup's LDS buffers.  Starts with a workgroup barrier, so
 // the LDS buffers may be reused by consecutive calls.
+//
+// Diagonal tiles are pair-once too (for W <= 8; larger blocks meet them as
+// masked ordered pairs): the rows of lane-slot k of wave wv form
+// the block's tile a = wv*K + k.  On diagonal tile t, row tile a < t meets
+// it pair-once, a == t meets it as ordered pairs with j == i removed by
+// index, and a > t skips it (that pair of tiles is met on diagonal tile a).
+// The j-side sums of a diagonal tile belong to rows of the same block; the
+// wave that holds tile t's rows adds them to its own accumulators.
 template <int W, int K>
 __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                                                 const float *__restrict__ m, int n, float eps2,
@@ -100,99 +222,58 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     __syncthreads();  // LDS buffers are free (callers may loop over blocks)
     for (int t = tid; t < W * 64; t += W * 64) (&jacc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 
-    // ---- this chunk's tiles: the block's TPB diagonal tiles followed by its
-    // ring tiles (delta-major), shared evenly among the C chunks.
+    // ---- this chunk's share of the block's tile sequence; tiles that hold
+    // only padding are skipped (uniform).
     const int U = TPB + ring_len(I, M) * TPB;
     const int u0 = (int)((long long)U * c / C);
     const int u1 = (int)((long long)U * (c + 1) / C);
+    // Small workgroups prefetch the next tile into registers while the
+    // current one is consumed; 16-wave blocks (one per CU, 128 VGPRs) have
+    // no registers to spare and rely on the other waves to hide the load.
+    constexpr bool kPrefetch = (W <= 8);
+    // Diagonal tiles pair-once (halves their work) where registers allow;
+    // 16-wave blocks meet them as masked ordered pairs (at 2^17 particles
+    // and up the diagonal is under 1/32 of the pairs).
+    constexpr bool kOnceDiag = (W <= 8);
+    int u = u0, delta = 0, jbase = 0;
+    for (; u < u1; ++u)
+        if ((jbase = tile_base<PB>(u, I, M, delta)) < n) break;
+    float4 next = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kPrefetch && u < u1 && tid < 64) next = load_particle(x, m, jbase + tid, n);
 
-    for (int u = u0; u < u1; ++u) {
-        int jbase, delta;
-        if (u < TPB) {
-            delta = 0;
-            jbase = I * PB + u * 64;
-        } else {
-            const int q = u - TPB;
-            delta = 1 + q / TPB;
-            const int t = q - (delta - 1) * TPB;
-            int J = I + delta;
-            if (J >= M) J -= M;
-            jbase = J * PB + t * 64;
-        }
-        if (jbase >= n) continue;  // an all-padding tile adds nothing (uniform branch)
-
-        __syncthreads();  // previous tile and its j-slot reduction are done
-        if (tid < 64) {
-            const int j = jbase + tid;
-            tile[tid] = (j < n) ? make_float4(x[3 * j], x[3 * j + 1], x[3 * j + 2], m[j])
-                                : make_float4(kPadCol, kPadCol, kPadCol, 0.0f);
-        }
+    while (u < u1) {
+        __syncthreads();  // previous tile and its j-slot sums are done
+        if (tid < 64) tile[tid] = kPrefetch ? next : load_particle(x, m, jbase + tid, n);
         __syncthreads();
+        const int cur_u = u, cur_delta = delta, cur_base = jbase;
+        for (++u; u < u1; ++u)
+            if ((jbase = tile_base<PB>(u, I, M, delta)) < n) break;
+        if (kPrefetch && u < u1 && tid < 64) next = load_particle(x, m, jbase + tid, n);
 
         float tx[K], ty[K], tz[K], tp[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = tp[k] = 0.0f;
 
-        if (delta == 0) {
-            // diagonal: ordered pairs, i-side only, j == i removed by index
+        const int t = cur_u;                         // diagonal tile index when cur_delta == 0
+        const bool diag = (cur_delta == 0);
+        float4 *slot = &jacc[wv][0];
+        if (!diag) {
+            tile_steps<K, false>(xi, yi, zi, mi, ii, tile, slot, lane, 0, 0, 0, eps2, tx, ty, tz, tp);
+        } else if (kOnceDiag) {
+            tile_steps<K, true>(xi, yi, zi, mi, ii, tile, slot, lane, wv * K, t, cur_base, eps2, tx,
+                                ty, tz, tp);
+        } else {
+            // ordered pairs, i-side only, j == i removed by index
             for (int s = 0; s < 64; ++s) {
                 const float4 q = tile[s];
-                const int j = jbase + s;
+                const int j = cur_base + s;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    pair_term_masked(xi[k], yi[k], zi[k], q, eps2, j == ii[k], tx[k], ty[k],
-                                     tz[k], tp[k]);
+                    pair_term_masked(xi[k], yi[k], zi[k], q, eps2, j == ii[k], tx[k], ty[k], tz[k],
+                                     tp[k]);
             }
-        } else {
-            float4 *slot = &jacc[wv][0];
-            float4 q = tile[lane];
-            for (int s = 0; s < 64; ++s) {
-                const int jj = (lane + s) & 63;
-                // Compiler-only barrier: this step's slot read stays after the
-                // previous step's slot write (another lane may have written it).
-                __asm__ volatile("" ::: "memory");
-                float4 acc = slot[jj];
-                const float4 qn = tile[(jj + 1) & 63];  // next step's particle (read-only tile)
-                float gx, gy, gz, gp;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float dx = xi[k] - q.x;
-                    const float dy = yi[k] - q.y;
-                    const float dz = zi[k] - q.z;
-                    float s2 = __builtin_fmaf(dx, dx, eps2);
-                    s2 = __builtin_fmaf(dy, dy, s2);
-                    s2 = __builtin_fmaf(dz, dz, s2);
-                    const float r = __builtin_amdgcn_rsqf(s2);
-                    const float r3 = r * (r * r);
-                    // i-side: + m_j r^3 d, + m_j r
-                    const float f = q.w * r3;
-                    tp[k] = __builtin_fmaf(q.w, r, tp[k]);
-                    tx[k] = __builtin_fmaf(f, dx, tx[k]);
-                    ty[k] = __builtin_fmaf(f, dy, ty[k]);
-                    tz[k] = __builtin_fmaf(f, dz, tz[k]);
-                    // j-side: - m_i r^3 d, + m_i r
-                    const float g = mi[k] * r3;
-                    if (k == 0) {
-                        gx = -g * dx;
-                        gy = -g * dy;
-                        gz = -g * dz;
-                        gp = mi[k] * r;
-                    } else {
-                        gx = __builtin_fmaf(-g, dx, gx);
-                        gy = __builtin_fmaf(-g, dy, gy);
-                        gz = __builtin_fmaf(-g, dz, gz);
-                        gp = __builtin_fmaf(mi[k], r, gp);
-                    }
-                }
-                acc.x += gx;
-                acc.y += gy;
-                acc.z += gz;
-                acc.w += gp;
-                slot[jj] = acc;
-                q = qn;
-            }
-            __asm__ volatile("" ::: "memory");
         }
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             ax[k] += tx[k];
@@ -200,23 +281,45 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
             az[k] += tz[k];
             ap[k] += tp[k];
         }
-        if (delta != 0) {
-            __syncthreads();  // every wave's j-side slots are complete
+        __syncthreads();  // every wave's j-side slots are complete
+        if (!diag) {
             if (tid < 64) {
-                float4 s = jacc[0][tid];
+                float4 sum = jacc[0][tid];
                 jacc[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int w2 = 1; w2 < W; ++w2) {
                     const float4 v = jacc[w2][tid];
-                    s.x += v.x;
-                    s.y += v.y;
-                    s.z += v.z;
-                    s.w += v.w;
+                    sum.x += v.x;
+                    sum.y += v.y;
+                    sum.z += v.z;
+                    sum.w += v.w;
                     jacc[w2][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                const int j = jbase + tid;
-                if (j < n) partial[(size_t)(C + delta - 1) * n + j] = s;
+                const int j = cur_base + tid;
+                if (j < n) partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
             }
+        } else if (kOnceDiag && wv == t / K) {
+            // this wave holds diagonal tile t's rows (lane-slot t % K)
+            float4 sum = jacc[0][lane];
+            jacc[0][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int w2 = 1; w2 < W; ++w2) {
+                const float4 v = jacc[w2][lane];
+                sum.x += v.x;
+                sum.y += v.y;
+                sum.z += v.z;
+                sum.w += v.w;
+                jacc[w2][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            const int kt = t - wv * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k == kt) {
+                    ax[k] += sum.x;
+                    ay[k] += sum.y;
+                    az[k] += sum.z;
+                    ap[k] += sum.w;
+                }
         }
     }
 
@@ -224,6 +327,5 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     for (int k = 0; k < K; ++k)
         if (ii[k] < n) partial[(size_t)c * n + ii[k]] = make_float4(ax[k], ay[k], az[k], ap[k]);
 }
-
 
 }  // namespace nbody

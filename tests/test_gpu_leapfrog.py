@@ -84,3 +84,27 @@ def test_velocity_adjoint_input(nb):
         e = np.abs(host(g) - r).max() / np.abs(r).max()
         print(f"[parity] leapfrog (x_T, v_T loss) grad {name} normwise {e:.2e}", flush=True)
         assert e <= 1e-3, name
+
+
+def test_full_config_against_oracle(nb):
+    # N = 16,384 Plummer, log-normal masses, eps2 = 1e-4, equilibrium
+    # velocities, 64 steps of dt = 1e-3, checkpoints every 8 steps, loss on
+    # the final positions: GPU gradient vs the FP64 reverse sweep, and its
+    # directional derivative vs a central difference of the FP64 integrator.
+    dev = need_gpu()
+    w = inputs.adjoint_16k()
+    x, v, m, u = w.x, w.extra["v0"], w.m, w.extra["u"]
+    _, gx, gv, gm = _grads(nb, x, v, m, u, w.eps2, 1e-3, 64, 8, dev)
+    rx, rv, rm = R.leapfrog_vjp(x, v, m, w.eps2, 1e-3, 64, u)
+    for g, r, name in ((gx, rx, "x0"), (gv, rv, "v0"), (gm, rm, "m")):
+        e = np.abs(host(g) - r).max() / np.abs(r).max()
+        print(f"[parity] leapfrog 16k grad {name} normwise {e:.2e}", flush=True)
+        assert e <= 1e-3, name
+    h = 1e-4
+    d = inputs.normal(x.shape, (72, 0)).astype(np.float64)
+    Lp = np.sum(u * R.leapfrog(x + h * d, v, m, w.eps2, 1e-3, 64)[0])
+    Lm = np.sum(u * R.leapfrog(x - h * d, v, m, w.eps2, 1e-3, 64)[0])
+    fd = (Lp - Lm) / (2 * h)
+    an = float(np.sum(host(gx) * d))
+    print(f"[parity] leapfrog 16k directional: GPU {an:.8e} FD {fd:.8e}", flush=True)
+    assert an == pytest.approx(fd, rel=1e-3)
