@@ -291,6 +291,48 @@ def main() -> int:
         }
         log(f"batched {kb:.3f} ms vs plain {wall_plain * 1e3:.1f} ms")
 
+    if not args.only_forward:
+        # -------------------- the paper's unrolling programs (Sec. IV, Fig. p)
+        log("unroll study")
+        wu = inputs.paper_experiment_set(3)
+        xu, mu = torch.from_numpy(wu[1]).to(dev), torch.from_numpy(wu[3]).to(dev)
+        names = nb.variant_names(nb.FORWARD)
+        study = {}
+        for label, vname in (("gpu-no-unrolling (K=1, U=1)", "fwd_b256_k1_u1"),
+                             ("simple-unrolling (K=4, U=1)", "fwd_b256_k4_u1"),
+                             ("double-unrolling (K=4, U=4)", "fwd_b256_k4_u4"),
+                             ("default", None)):
+            nb.set_variant(nb.FORWARD, names.index(vname) if vname else -1)
+            f = lambda: nb.forces(xu, mu, wu[4])
+            f()
+            wl, km, cm = timed_calls(f, 10, torch, nb)
+            pr = metrics.pairs(xu.shape[0]) / (wl / 10)
+            study[label] = {"variant": vname or names[nb.selected_variant(nb.FORWARD, xu.shape[0])],
+                            "ms": wl * 100, "pairs_per_s": pr,
+                            "gflops_38": pr * 38 / 1e9}
+        nb.set_variant(nb.FORWARD, -1)
+        out["unroll_study_n100000"] = study
+
+        # ---------------- Experiment 2 of the paper: 100 leap-frog steps
+        log("paper experiment 2 stand-ins")
+        from paper_0904_3659_amd import leapfrog as LF
+        paper_s = {"three_figure_eight_galaxies": 0.68, "four_figure_eight_galaxies": 0.92,
+                   "cart_wheel_galaxy": 2.43, "random_100000_body": 55.0}
+        exp2 = {}
+        for k in range(4):
+            name, x0, v0, m0, e2, dt = inputs.paper_experiment_set(k)
+            xt, vt, mt = (torch.from_numpy(t).to(dev) for t in (x0, v0, m0))
+            LF.integrate(xt, vt, mt, e2, dt, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            LF.integrate(xt, vt, mt, e2, dt, 100)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            exp2[name] = {"n": int(x0.shape[0]), "dt": dt, "eps2": e2, "seconds_100_steps": secs,
+                          "paper_double_unrolling_seconds": paper_s[name],
+                          "speedup_vs_paper": paper_s[name] / secs}
+        out["paper_experiment2_standins"] = exp2
+
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(w)

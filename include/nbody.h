@@ -148,6 +148,16 @@ nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems,
  */
 nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, void *stream);
 
+/*
+ * Kick and drift of one leap-frog step in one pass (Eqs. (1)-(2), Sec. III):
+ *     v += kick * a;  x += dt * v        (x, v, a: [n][3], float32 FMA)
+ * With the paper's a, kick = -dt/2 (the physical acceleration is -a).
+ * Errors: n < 0 or > NBODY_MAX_N, NULL with n > 0, kick or dt not finite,
+ * overlapping arrays -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_kick_drift(float *x, float *v, const float *a, int64_t n, float kick, float dt,
+                              void *stream);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Number of compiled kernel variants for a kind (0 for an unknown kind). */

@@ -352,7 +352,11 @@ int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
 
 const char *nbody_status_string(nbody_status status)
 {
-    switch (status) {
+    // A C caller may pass any int; read it as one (an out-of-range value of
+    // the enum type would be undefined behaviour in C++).
+    int code;
+    std::memcpy(&code, &status, sizeof code);
+    switch (code) {
     case NBODY_OK: return "NBODY_OK";
     case NBODY_ERROR_INVALID_ARGUMENT: return "NBODY_ERROR_INVALID_ARGUMENT";
     case NBODY_ERROR_UNSUPPORTED_DEVICE: return "NBODY_ERROR_UNSUPPORTED_DEVICE";
@@ -462,6 +466,24 @@ nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, voi
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     return axpy_run(y, xv, len, alpha, (hipStream_t)stream);
+}
+
+nbody_status nbody_kick_drift(float *x, float *v, const float *a, int64_t n, float kick, float dt,
+                              void *stream)
+{
+    clear_error();
+    if (n < 0 || n > NBODY_MAX_N) return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+    if (!std::isfinite(kick) || !std::isfinite(dt))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "kick and dt must be finite");
+    if (n == 0) return NBODY_OK;
+    if (!x || !v || !a) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x, v or a with n = %lld", (long long)n);
+    const size_t b = 12 * (size_t)n;
+    if (overlaps(x, b, v, b) || overlaps(x, b, a, b) || overlaps(v, b, a, b))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "x, v and a overlap");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return kick_drift_run(x, v, a, 3 * n, kick, dt, (hipStream_t)stream);
 }
 
 int nbody_variant_count(int kind) { return variant_count(kind); }

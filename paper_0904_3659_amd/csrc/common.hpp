@@ -85,6 +85,8 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
 
 // ---- elementwise
 nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipStream_t stream);
+nbody_status kick_drift_run(float *x, float *v, const float *a, int64_t len, float kick, float dt,
+                            hipStream_t stream);
 // Deterministic timing inputs (unit cube, masses 1/n, weights in [-1,1));
 // w and v may be NULL.
 nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint32_t seed,

@@ -16,6 +16,21 @@ __global__ __launch_bounds__(256) void axpy_kernel(float *__restrict__ y,
         y[t] = __builtin_fmaf(alpha, xv[t], y[t]);
 }
 
+// Kick then drift of one leap-frog step, Eqs. (1)-(2): v += kick * a, then
+// x += dt * v (with the kicked v), in one pass over the particles.
+__global__ __launch_bounds__(256) void kick_drift_kernel(float *__restrict__ x,
+                                                         float *__restrict__ v,
+                                                         const float *__restrict__ a, int64_t len,
+                                                         float kick, float dt)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += stride) {
+        const float vh = __builtin_fmaf(kick, a[t], v[t]);
+        v[t] = vh;
+        x[t] = __builtin_fmaf(dt, vh, x[t]);
+    }
+}
+
 // 32-bit integer hash (Wang/Jenkins-style mixing) -> uniform float in [0,1).
 __device__ __forceinline__ float hash_unit(uint32_t v)
 {
@@ -56,6 +71,17 @@ nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipSt
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
     hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, y, xv, len, alpha);
     return check_launch("axpy");
+}
+
+nbody_status kick_drift_run(float *x, float *v, const float *a, int64_t len, float kick, float dt,
+                            hipStream_t stream)
+{
+    int64_t blocks = (len + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    hipLaunchKernelGGL(kick_drift_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, v, a, len,
+                       kick, dt);
+    return check_launch("kick_drift");
 }
 
 nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint32_t seed,

@@ -177,6 +177,11 @@ struct Variant {
 #define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O}
 
 const Variant kVariants[] = {
+    // The paper's three GPU programs as (rows per lane K, j-unroll U):
+    // gpu-no-unrolling (1, 1), simple-unrolling (4, 1) and double-unrolling
+    // (4, 4) of Figs. no-u, sim-u and double-u (Sec. IV).
+    FWD_VARIANT(256, 1, 1),
+    FWD_VARIANT(256, 4, 1),
     FWD_VARIANT(256, 4, 4),
     FWD_VARIANT(256, 2, 8),
     FWD_VARIANT(256, 1, 8),
@@ -220,7 +225,7 @@ int forward_default_variant(int64_t n)
     static const int gather_big = variant_index("fwd_b64_k1_u8");
     static const int gather_mid = variant_index("fwd_b256_k1_u8");
     static const int gather_small = variant_index("fwd_b128_k1_u8");
-    static const int pair_once_mid = variant_index("fwd_sym_w4_k4_o1");
+    static const int pair_once_mid = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_big = variant_index("fwd_sym_w16_k4_o1");
     if (n > (1 << 21)) return gather_big;
     if (n >= (1 << 17)) return pair_once_big;

@@ -215,3 +215,30 @@ def ensemble_4096(num_systems: int = 4096, nmin: int = 8, nmax: int = 2048) -> E
     sizes = rng(5, 0).integers(nmin, nmax + 1, num_systems)
     return ensemble(sizes, key=(5,), eps2=1e-4,
                     name=f"ensemble_{num_systems}x_n{nmin}-{nmax}_eq_eps2_1e-4")
+
+
+# Stand-ins for the four inputs of the paper's experiments (Sec. V-A): three
+# galaxy sets (figure-eight groups of 7,500 and 10,000 bodies, a cart-wheel
+# collision of 18,000) and a random 100,000-body set, with the time steps and
+# softening lengths the paper lists.  The galaxy initial conditions are not
+# published; Plummer spheres with equilibrium velocities take their place,
+# and the random set is uniform in the unit cube with velocities uniform in
+# [-0.1, 0.1)^3.  Masses are 1/N.
+PAPER_EXPERIMENT_SETS = (
+    ("three_figure_eight_galaxies", 7500, 0.015625, 0.1),
+    ("four_figure_eight_galaxies", 10000, 0.015625, 0.1),
+    ("cart_wheel_galaxy", 18000, 0.0078125, 0.01),
+    ("random_100000_body", 100000, 0.01, 0.01),
+)
+
+
+def paper_experiment_set(index: int):
+    """(name, x0, v0, m, eps2, dt) of stand-in ``index`` (0..3)."""
+    name, n, dt, eps = PAPER_EXPERIMENT_SETS[index]
+    if index < 3:
+        x = plummer_positions(n, (6, index, 0))
+        v = plummer_velocities(x, (6, index, 1))
+    else:
+        x = uniform_cube(n, (6, index, 0))
+        v = _f32(rng(6, index, 1).uniform(-0.1, 0.1, (n, 3)))
+    return name, x, v, equal_masses(n), eps * eps, dt

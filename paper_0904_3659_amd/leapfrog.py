@@ -6,7 +6,8 @@ the next step's first kick.  The paper's a (Eq. (gravity)) points away from
 the attracting body, so the physical acceleration is g = -a and a kick is
 v += (dt/2) g = v - (dt/2) a.  Every step is a library call: the force
 evaluation (``nbody_forces``), its adjoint (``nbody_forces_backward``) and
-the kick/drift updates (``nbody_axpy``); tensors only hold device memory.
+the kick/drift updates (``nbody_kick_drift``, ``nbody_axpy``); tensors only
+hold device memory.
 
 Reverse sweep for a loss on the final state.  With adjoints (lx, lv) of the
 step output (x_t, v_t), stepping back over step t-1 is
@@ -33,10 +34,9 @@ from . import nbody as _nb
 
 def _step(x, v, a, m, eps2, dt):
     """One KDK step in place; `a` holds a(x) on entry and a(x') on exit."""
-    _nb.axpy_(v, a, -0.5 * dt)
-    _nb.axpy_(x, v, dt)
+    _nb.kick_drift_(x, v, a, -0.5 * dt, dt)      # Eqs. (1)-(2)
     _nb.forces(x, m, eps2, out=(a, None), potential=False)
-    _nb.axpy_(v, a, -0.5 * dt)
+    _nb.axpy_(v, a, -0.5 * dt)                   # Eq. (3)
 
 
 def integrate(x0, v0, m, eps2, dt, steps, *, keep_every: int | None = None):

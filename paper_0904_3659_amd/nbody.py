@@ -60,6 +60,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_forces_backward.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp, _vp, _vp]
         L.nbody_forces_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp, _vp, _vp]
         L.nbody_axpy.argtypes = [_vp, _vp, _i64, _f32, _vp]
+        L.nbody_kick_drift.argtypes = [_vp, _vp, _vp, _i64, _f32, _f32, _vp]
         L.nbody_variant_count.argtypes = [ctypes.c_int]
         L.nbody_variant_count.restype = ctypes.c_int
         L.nbody_variant_name.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -73,6 +74,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
         L.nbody_selected_variant.restype = ctypes.c_int
         for f in ("nbody_forces", "nbody_forces_backward", "nbody_forces_batched", "nbody_axpy",
+                  "nbody_kick_drift",
                   "nbody_set_variant", "nbody_autotune", "nbody_release_workspace",
                   "nbody_profile_enable", "nbody_profile_read"):
             getattr(L, f).restype = ctypes.c_int
@@ -210,6 +212,18 @@ def axpy_(y: torch.Tensor, xv: torch.Tensor, alpha: float) -> torch.Tensor:
     with torch.cuda.device(y.device):
         _check(lib().nbody_axpy(_ptr(y), _ptr(xv), y.numel(), float(alpha), _stream(y.device)))
     return y
+
+
+def kick_drift_(x: torch.Tensor, v: torch.Tensor, a: torch.Tensor, kick: float, dt: float):
+    """In place v += kick * a, then x += dt * v (one leap-frog kick + drift)."""
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    _want(v, "v", (n, 3), x.device)
+    _want(a, "a", (n, 3), x.device)
+    with torch.cuda.device(x.device):
+        _check(lib().nbody_kick_drift(_ptr(x), _ptr(v), _ptr(a), n, float(kick), float(dt),
+                                      _stream(x.device)))
+    return x, v
 
 
 # ---------------------------------------------------------------- autograd

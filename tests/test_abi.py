@@ -129,3 +129,13 @@ def test_autotune_validation(L):
     assert L.nbody_autotune(0, s.ctypes.data_as(ctypes.POINTER(i64)), 1, None) == 1
     assert L.nbody_autotune(9, s.ctypes.data_as(ctypes.POINTER(i64)), 1, None) == 1
     assert L.nbody_autotune(0, None, 0, None) == 0
+
+
+def test_kick_drift_validation(L):
+    L.nbody_kick_drift.argtypes = [vp, vp, vp, i64, f32, f32, vp]
+    assert L.nbody_kick_drift(FAKE, FAKE, FAKE, -1, 0.1, 0.1, None) == 1
+    assert L.nbody_kick_drift(FAKE, ctypes.c_void_p(0x90000), ctypes.c_void_p(0xA0000), 4,
+                              float("inf"), 0.1, None) == 1
+    assert L.nbody_kick_drift(FAKE, ctypes.c_void_p(0x10004), ctypes.c_void_p(0xA0000), 4,
+                              0.1, 0.1, None) == 1
+    assert L.nbody_kick_drift(None, None, None, 0, 0.1, 0.1, None) == 0

@@ -72,3 +72,10 @@ def test_ensemble_layout():
     # system k is the same whatever the other systems are
     other = inputs.ensemble([s[0], 5], key=(5,))
     assert np.array_equal(other.x[: s[0]], ens.x[: s[0]])
+
+
+def test_paper_experiment_standins():
+    for k, (name, n, dt, eps) in enumerate(inputs.PAPER_EXPERIMENT_SETS):
+        nm, x, v, m, e2, dt2 = inputs.paper_experiment_set(k)
+        assert nm == name and x.shape == (n, 3) and v.shape == (n, 3) and m.shape == (n,)
+        assert e2 == pytest.approx(eps * eps) and dt2 == dt
