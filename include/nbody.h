@@ -120,10 +120,11 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
  * itself.  `offsets` is a HOST array of num_systems + 1 int64 values with
  * offsets[0] == 0, non-decreasing; the total is offsets[num_systems].
  * Empty systems are allowed.  The library builds a work plan from the
- * offsets (a cost-ordered list of units: (system, 192-particle block) for
+ * offsets (a cost-ordered list of units: (system, 256-particle block) for
  * the default pair-once variant, (system, i-tile) for gather variants),
  * caches it keyed by the offsets' content, uploads it to library memory and
- * runs one persistent launch (plus one launch that adds the pair-once
+ * runs one persistent launch whose workgroups draw units largest-first from
+ * a per-stream ticket counter (plus one launch that adds the pair-once
  * partial sums; about 16 (1 + M_s/2) N_s bytes of workspace per system of
  * N_s particles in M_s blocks).  Per-system results equal nbody_forces on that system
  * up to float32 summation order, and are bitwise independent of the other

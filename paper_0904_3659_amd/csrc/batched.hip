@@ -10,10 +10,12 @@
 //   workgroups in a snake order (g, 2G-1-g, 2G+g, ...), which balances the
 //   static schedule without atomics or counters.
 //
-// Pair-once variants (bat_sym_*): a unit is (system s, block I) and runs the
-// pair-once block evaluation of pair_once.hpp on that system alone (one
-// chunk per block); its partial slots live in a per-plan region of library
-// workspace, and a second launch adds each particle's slots in fixed order.
+// Pair-once variants (bat_sym_*, bat_symd_*): a unit is (system s, block I)
+// and runs the pair-once block evaluation of pair_once.hpp on that system
+// alone (one chunk per block); its partial slots live in a per-plan region of
+// library workspace, and a second launch adds each particle's slots in fixed
+// order.  bat_symd_* take units from a ticket counter instead of the static
+// snake deal.
 //
 // Kernel: a grid of exactly as many workgroups as the device holds at once;
 // workgroup g walks its units, staging each system's j-range through LDS
@@ -134,6 +136,40 @@ __global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
     }
 }
 
+// The same units taken dynamically: workgroups draw the next unit of the
+// cost-sorted list from a ticket counter (largest first, then whoever is
+// free takes the next), which balances the tail better than a static deal
+// when units of equal estimated cost run at different speeds.  The last
+// workgroup to finish resets the counters for the next launch on the stream.
+template <int W, int K>
+__global__ __launch_bounds__(W * 64) void batched_sym_dyn_kernel(BatSymArgs A, int *ctr)
+{
+    constexpr int PB = W * 64 * K;
+    __shared__ float4 tile[64];
+    __shared__ float4 jacc[W][64];
+    __shared__ int s_idx;
+    for (;;) {
+        __syncthreads();  // every thread has read the previous ticket
+        if (threadIdx.x == 0) s_idx = atomicAdd(ctr, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        if (idx >= A.num_units) break;
+        const int4 u = A.units[idx];
+        const int ns = u.y;
+        const int M = (ns + PB - 1) / PB;
+        pair_once_block<W, K>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
+                              A.partial + u.w, tile, jacc);
+    }
+    if (threadIdx.x == 0) {
+        // Every workgroup draws tickets until it fails once and only then
+        // counts itself done, so the last one to count sees no more draws.
+        if (atomicAdd(ctr + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(ctr, 0);
+            atomicExch(ctr + 1, 0);
+        }
+    }
+}
+
 // a, p of block I of system s = its slots (i-side, then the ring slots the
 // block received), added in slot order.  One workgroup per unit.
 template <int PB>
@@ -168,6 +204,7 @@ __global__ __launch_bounds__(256) void batched_sym_reduce_kernel(const int4 *__r
 using KernelFn = void (*)(BatArgs);
 using SymKernelFn = void (*)(BatSymArgs);
 using SymReduceFn = void (*)(const int4 *, const float4 *, float *, float *);
+using SymDynKernelFn = void (*)(BatSymArgs, int *);
 
 struct Variant {
     const char *name;
@@ -177,12 +214,16 @@ struct Variant {
     SymKernelFn sym_fn;
     SymReduceFn sym_reduce;
     int sym_threads;
+    SymDynKernelFn sym_dyn;  // dynamic-ticket pair-once kernel (sym_fn unused)
 };
 
-#define BAT_VARIANT(B, U) {"bat_b" #B "_u" #U, B, U, batched_kernel<B, U>, 0, nullptr, nullptr, 0}
+#define BAT_VARIANT(B, U) {"bat_b" #B "_u" #U, B, U, batched_kernel<B, U>, 0, nullptr, nullptr, 0, nullptr}
 #define BAT_SYM_VARIANT(W, K) \
     {"bat_sym_w" #W "_k" #K, 0, 0, nullptr, W * 64 * K, batched_sym_kernel<W, K>, \
-     batched_sym_reduce_kernel<W * 64 * K>, W * 64}
+     batched_sym_reduce_kernel<W * 64 * K>, W * 64, nullptr}
+#define BAT_SYMD_VARIANT(W, K) \
+    {"bat_symd_w" #W "_k" #K, 0, 0, nullptr, W * 64 * K, batched_sym_kernel<W, K>, \
+     batched_sym_reduce_kernel<W * 64 * K>, W * 64, batched_sym_dyn_kernel<W, K>}
 
 const Variant kVariants[] = {
     BAT_VARIANT(64, 8),
@@ -194,6 +235,9 @@ const Variant kVariants[] = {
     BAT_SYM_VARIANT(2, 2),
     BAT_SYM_VARIANT(1, 8),
     BAT_SYM_VARIANT(2, 4),
+    BAT_SYMD_VARIANT(1, 3),
+    BAT_SYMD_VARIANT(1, 4),
+    BAT_SYMD_VARIANT(1, 2),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -281,7 +325,9 @@ nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
     plan->num_units = (int)host.size();
 
     int per_cu = 0;
-    hipError_t e = V.sym_pb
+    hipError_t e = V.sym_dyn
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.sym_dyn, V.sym_threads, 0)
+        : V.sym_pb
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.sym_fn, V.sym_threads, 0)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.fn, V.block, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
@@ -324,11 +370,12 @@ const char *batched_variant_name(int index)
 }
 
 // Measured on MI355X (4,096 Plummer systems of 8..2048 particles): the
-// pair-once variant with 192-particle blocks is fastest; very small systems
-// gain nothing from pairing and take the gather variant.
+// pair-once variant with 256-particle blocks drawn from the ticket counter
+// is fastest; very small systems gain nothing from pairing and take the
+// gather variant.
 int batched_default_variant(int64_t mean_n)
 {
-    static const int pair_once = variant_index("bat_sym_w1_k3");
+    static const int pair_once = variant_index("bat_symd_w1_k4");
     static const int gather = variant_index("bat_b64_u8");
     return mean_n >= 128 ? pair_once : gather;
 }
@@ -353,9 +400,17 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
         st = workspace(dev, stream, sizeof(float4) * plan->partial_elems, &ws);
         if (st != NBODY_OK) return st;
         BatSymArgs S{plan->d_units, plan->num_units, x, m, eps2, static_cast<float4 *>(ws)};
+        int *ctr = nullptr;
+        if (V.sym_dyn) {
+            st = counters(dev, stream, 2, &ctr);
+            if (st != NBODY_OK) return st;
+        }
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
         prof_mark(stream, 0);
-        hipLaunchKernelGGL(V.sym_fn, dim3(plan->grid), dim3(V.sym_threads), 0, stream, S);
+        if (V.sym_dyn)
+            hipLaunchKernelGGL(V.sym_dyn, dim3(plan->grid), dim3(V.sym_threads), 0, stream, S, ctr);
+        else
+            hipLaunchKernelGGL(V.sym_fn, dim3(plan->grid), dim3(V.sym_threads), 0, stream, S);
         prof_mark(stream, 1);
         st = check_launch(V.name);
         if (st != NBODY_OK) return st;

@@ -143,6 +143,45 @@ nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void
     return NBODY_OK;
 }
 
+namespace {
+struct CounterBuf {
+    int *ptr = nullptr;
+    size_t count = 0;
+};
+std::mutex g_cnt_mu;
+std::map<std::pair<int, hipStream_t>, CounterBuf> g_cnt;
+}  // namespace
+
+nbody_status counters(const Device &dev, hipStream_t stream, size_t count, int **ptr)
+{
+    if (fault_injected("alloc")) return fail(NBODY_ERROR_OUT_OF_MEMORY, "injected allocation fault");
+    std::lock_guard<std::mutex> lock(g_cnt_mu);
+    CounterBuf &b = g_cnt[{dev.id, stream}];
+    if (b.count < count) {
+        if (b.ptr) {
+            hipError_t e = hipFree(b.ptr);  // waits for the device
+            b.ptr = nullptr;
+            b.count = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(counters)");
+        }
+        const size_t grow = std::max(count, (size_t)256);
+        hipError_t e = hipMalloc(&b.ptr, grow * sizeof(int));
+        if (e != hipSuccess) {
+            b.ptr = nullptr;
+            return hip_fail(e, "hipMalloc(counters)");
+        }
+        nbody_status st = fill_zero_int(b.ptr, grow, stream);
+        if (st != NBODY_OK) {
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            return st;
+        }
+        b.count = grow;
+    }
+    *ptr = b.ptr;
+    return NBODY_OK;
+}
+
 // ---------------------------------------------------------------- profiling
 
 namespace {
@@ -525,6 +564,18 @@ nbody_status nbody_release_workspace(void)
         }
     }
     g_ws.clear();
+    std::lock_guard<std::mutex> lock2(g_cnt_mu);
+    for (auto &kv : g_cnt) {
+        if (kv.second.ptr) {
+            int cur = -1;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(kv.first.first);
+            hipError_t e = hipFree(kv.second.ptr);
+            (void)hipSetDevice(cur);
+            if (e != hipSuccess && st == NBODY_OK) st = hip_fail(e, "hipFree(counters)");
+        }
+    }
+    g_cnt.clear();
     return st;
 }
 

@@ -34,6 +34,11 @@ nbody_status current_device(Device *dev);
 // asks for more bytes, or nbody_release_workspace().
 nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr);
 
+// Per-(device, stream) array of at least `count` int counters that are zero
+// between calls (kernels that use them leave them at zero); zero-filled
+// with a kernel when first allocated or grown.
+nbody_status counters(const Device &dev, hipStream_t stream, size_t count, int **ptr);
+
 // NBODY_FAULT=<what> makes the named step report failure (tests of the
 // error paths; checked on the host before anything is launched).
 bool fault_injected(const char *what);
@@ -87,6 +92,9 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
 nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipStream_t stream);
 nbody_status kick_drift_run(float *x, float *v, const float *a, int64_t len, float kick, float dt,
                             hipStream_t stream);
+// Zero len ints with a fill kernel on `stream` (no hipMemsetAsync, so the
+// work can sit in a captured graph).
+nbody_status fill_zero_int(int *p, size_t len, hipStream_t stream);
 // Deterministic timing inputs (unit cube, masses 1/n, weights in [-1,1));
 // w and v may be NULL.
 nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint32_t seed,

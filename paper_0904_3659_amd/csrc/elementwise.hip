@@ -62,7 +62,20 @@ __global__ __launch_bounds__(256) void fill_kernel(float *x, float *m, float *w,
     if (v) v[i] = 2.0f * hash_unit(b + 6) - 1.0f;
 }
 
+__global__ __launch_bounds__(256) void zero_int_kernel(int *p, int64_t len)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) p[i] = 0;
+}
+
 }  // namespace
+
+nbody_status fill_zero_int(int *p, size_t len, hipStream_t stream)
+{
+    hipLaunchKernelGGL(zero_int_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, stream, p,
+                       (int64_t)len);
+    return check_launch("zero_int");
+}
 
 nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipStream_t stream)
 {
