@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-interactions/s & % FP32 VALU peak (38 flop/pair): fwd, adjoint, batched"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_plummer_n1048576_traffic.txt")
 FORWARD_SOURCES = [os.path.join(ROOT, "paper_0904_3659_amd", "csrc", f)
-                   for f in ("forward.hip", "forward_sym.hip", "pair_once.hpp", "common.hpp")]
+                   for f in ("forward_sym.hip", "pair_once.hpp", "common.hpp")]
 
 
 def log(msg: str) -> None:
@@ -43,9 +43,10 @@ def forward_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(variant: str):
     """HBM bytes per launch of the forward kernel from the committed counter
-    summary, or None if absent or taken on a different kernel source."""
+    summary, or None if absent, taken on another variant, or taken on a
+    different source of the pair-once kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -53,7 +54,7 @@ def read_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha") != forward_source_sha():
+    if kv.get("kernel_source_sha") != forward_source_sha() or kv.get("variant") != variant:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -156,8 +157,8 @@ def main() -> int:
     value = pairs / (wall / args.steps)
     achieved = pairs * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3) / 1e12
     peak = metrics.MI355X_FP32_VECTOR_TFLOPS
-    traffic = read_traffic()
     variant = nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, w.n)]
+    traffic = read_traffic(variant)
     log(f"forward {ms_step:.2f} ms/step, {value:.3e} pairs/s, kernel {kern_ms:.2f} ms")
 
     out = {

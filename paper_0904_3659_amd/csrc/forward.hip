@@ -160,6 +160,72 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float4 *__rest
     if (p) p[i] = s.w;
 }
 
+// ---------------------------------------------------------------------------
+// Single-launch gather for small n: a workgroup owns 64 rows (one per lane,
+// the same rows in all W waves) and splits j among its waves; wave w sums
+// j in [w * chunk, (w+1) * chunk) through its own 64-particle LDS tiles, and
+// the W partial sums of each row are added in wave order through LDS.  No
+// second launch and no partial buffer: at n of a few thousand the launch
+// and the reduction, not the pairs, dominate the split gather.
+template <int W>
+__global__ __launch_bounds__(W * 64) void forward_wsplit_kernel(FwdArgs P)
+{
+    __shared__ float4 tiles[W][64];
+    __shared__ float4 red[W][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int n = P.n;
+    const float eps2 = P.eps2;
+    const int i = blockIdx.x * 64 + lane;
+    const int ic = i < n ? i : n - 1;
+    const float xi = P.x[3 * ic], yi = P.x[3 * ic + 1], zi = P.x[3 * ic + 2];
+    const int jb = wv * P.chunk;
+    const int je = min(n, jb + P.chunk);
+    const int row0 = blockIdx.x * 64;
+    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+    float4 *tile = tiles[wv];
+    for (int t0 = jb; t0 < je; t0 += 64) {
+        const int j = t0 + lane;
+        // Compiler-only barriers around the wave-private tile: the previous
+        // tile's reads finish before this write, and this write precedes the
+        // reads below (one wave's LDS accesses complete in issue order).
+        __asm__ volatile("" ::: "memory");
+        tile[lane] = (j < je) ? make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j])
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        __asm__ volatile("" ::: "memory");
+        float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
+        const int cnt = min(64, je - t0);
+        if (cnt == 64 && (t0 >= row0 + 64 || t0 + 64 <= row0)) {
+#pragma unroll 8
+            for (int s = 0; s < 64; ++s) pair_term(xi, yi, zi, tile[s], eps2, tx, ty, tz, tp);
+        } else {
+            for (int s = 0; s < cnt; ++s)
+                pair_term_masked(xi, yi, zi, tile[s], eps2, t0 + s == i, tx, ty, tz, tp);
+        }
+        ax += tx;
+        ay += ty;
+        az += tz;
+        ap += tp;
+    }
+    red[wv][lane] = make_float4(ax, ay, az, ap);
+    __syncthreads();
+    if (wv == 0 && i < n) {
+        float4 s = red[0][lane];
+#pragma unroll
+        for (int w2 = 1; w2 < W; ++w2) {
+            const float4 q = red[w2][lane];
+            s.x += q.x;
+            s.y += q.y;
+            s.z += q.z;
+            s.w += q.w;
+        }
+        P.a[3 * i + 0] = s.x;
+        P.a[3 * i + 1] = s.y;
+        P.a[3 * i + 2] = s.z;
+        if (P.p) P.p[i] = s.w;
+    }
+}
+
 using KernelFn = void (*)(FwdArgs);
 
 // A variant is either a gather kernel (every ordered pair, rows own all j)
@@ -170,11 +236,13 @@ struct Variant {
     int block, k, unroll;
     KernelFn direct, partial;
     int sym_w, sym_k, sym_occ;
+    int wsplit_w;  // > 0: single-launch gather with this many j-split waves
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0}
-#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, 0}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, 0}
+#define FWD_WSPLIT_VARIANT(W) {"fwd_wsplit_w" #W, 64, 1, 0, forward_wsplit_kernel<W>, nullptr, 0, 0, 0, W}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -197,6 +265,9 @@ const Variant kVariants[] = {
     FWD_SYM_VARIANT(4, 4, 1),
     FWD_SYM_VARIANT(2, 8, 1),
     FWD_SYM_VARIANT(16, 4, 1),
+    FWD_WSPLIT_VARIANT(16),
+    FWD_WSPLIT_VARIANT(8),
+    FWD_WSPLIT_VARIANT(4),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -224,14 +295,19 @@ int forward_default_variant(int64_t n)
 {
     static const int gather_big = variant_index("fwd_b64_k1_u8");
     static const int gather_mid = variant_index("fwd_b256_k1_u8");
-    static const int gather_small = variant_index("fwd_b128_k1_u8");
+    static const int wsplit_8 = variant_index("fwd_wsplit_w8");
+    static const int wsplit_16 = variant_index("fwd_wsplit_w16");
     static const int pair_once_mid = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_big = variant_index("fwd_sym_w16_k4_o1");
     if (n > (1 << 21)) return gather_big;
     if (n >= (1 << 17)) return pair_once_big;
     if (n >= (1 << 15)) return pair_once_mid;
+    // The single-launch gather has one workgroup per 64 rows and so cannot
+    // balance row counts that are not near a multiple of the CU count; it
+    // serves only sizes where launch latency, not the pairs, sets the time.
     if (n >= (1 << 12)) return gather_mid;
-    return gather_small;
+    if (n >= (1 << 11)) return wsplit_16;
+    return wsplit_8;
 }
 
 // Number of j-splits: enough workgroups to give every CU several, never a
@@ -250,6 +326,17 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          float eps2, float *a, float *p, hipStream_t stream)
 {
     const Variant &V = kVariants[variant];
+    if (V.wsplit_w) {
+        // j chunk per wave: a multiple of 64, every wave at least one tile
+        int chunk = (n + V.wsplit_w - 1) / V.wsplit_w;
+        chunk = (chunk + 63) / 64 * 64;
+        FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p};
+        if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
+        hipLaunchKernelGGL(V.direct, dim3((n + 63) / 64), dim3(V.wsplit_w * 64), 0, stream, P);
+        prof_mark(stream, 1);
+        return check_launch(V.name);
+    }
     if (V.sym_w)
         return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream);
     const int iblk = V.block * V.k;

@@ -177,20 +177,24 @@ def test_invalid_arguments(nb):
     assert ei.value.status == 1
 
 
-def test_fault_injection_then_recovery(nb):
+@pytest.mark.parametrize("n", [1024, 5000])
+def test_fault_injection_then_recovery(nb, n):
     dev = need_gpu()
-    w = inputs.plummer_1k()
-    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
-    good, _ = nb.forces(x, m, w.eps2)
-    for what, status in (("launch", 4), ("alloc", 3)):
+    x = to_dev(inputs.plummer_positions(n, (62, n)), dev)
+    m = to_dev(inputs.equal_masses(n), dev)
+    good, _ = nb.forces(x, m, 1e-4)
+    # n = 5000 takes the split gather, which needs a partial-sum workspace;
+    # n = 1024 takes the single-launch gather, which needs none
+    faults = (("launch", 4), ("alloc", 3)) if n == 5000 else (("launch", 4),)
+    for what, status in faults:
         os.environ["NBODY_FAULT"] = what
         try:
             with pytest.raises(nb.NBodyError) as ei:
-                nb.forces(x, m, w.eps2)   # n = 1024 uses j-splits, so it allocates
+                nb.forces(x, m, 1e-4)
             assert ei.value.status == status
         finally:
             del os.environ["NBODY_FAULT"]
-    again, _ = nb.forces(x, m, w.eps2)
+    again, _ = nb.forces(x, m, 1e-4)
     assert torch.equal(good, again)
 
 
@@ -220,6 +224,8 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 65536)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
+    # single-launch j-split gather: no partial buffer, no reduction launch
+    assert names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_wsplit")
 
 
 def test_profile_hook(nb):
