@@ -80,9 +80,10 @@ const char *nbody_last_error(void);
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair); it needs about 8 n^2 / 4096 bytes of
  * library workspace above 2^17 particles (2.1 GB at n = 2^20).  Outside that range the default
- * gathers every ordered pair per row: below 2^12 in one launch whose workgroups
- * split j among their waves (no workspace), otherwise with j-splits across
- * workgroups and a reduction launch (at most 16 n * splits bytes).
+ * gathers every ordered pair per row with j-splits: below 2^13 in one launch
+ * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
+ * workspace and one int counter per 64 rows), otherwise with a reduction
+ * launch (at most 16 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
  *

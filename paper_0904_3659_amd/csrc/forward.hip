@@ -27,6 +27,7 @@
 // and split count.
 #include "common.hpp"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 
@@ -161,34 +162,60 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float4 *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Single-launch gather for small n: a workgroup owns 64 rows (one per lane,
-// the same rows in all W waves) and splits j among its waves; wave w sums
-// j in [w * chunk, (w+1) * chunk) through its own 64-particle LDS tiles, and
-// the W partial sums of each row are added in wave order through LDS.  No
-// second launch and no partial buffer: at n of a few thousand the launch
-// and the reduction, not the pairs, dominate the split gather.
+// One-launch split gather for small n, where launch latency and not the
+// pairs sets the time.  A workgroup of W waves owns 64 rows (one per lane,
+// the same rows in every wave) and splits j among its waves; S such
+// workgroups per row block along grid.y spread the j-range over the chip.
+// Workgroup (b, s) owns rows [64 b, 64 b + 64) and its wave w sums
+// j in [(s W + w) chunk, (s W + w + 1) chunk) through a wave-private LDS
+// tile.  The W wave sums are added in wave order through LDS; with S = 1
+// they are the result, otherwise they are stored as the split's float4
+// partial and the last workgroup of row block b to arrive (a ticket counter
+// per row block) adds the S partials in split order, stores a, p and puts
+// the counter back to zero for the next launch.  Which workgroup arrives
+// last varies from run to run, but the order of every addition does not:
+// the result is bitwise reproducible for a given n, W and S.
+//
+// The agent-scope fences around the ticket write back and invalidate the
+// XCD's L2, so the scheme pays off only with few workgroups: the same tail
+// on the 256-row split gather (about 1000 workgroups at n = 7500) ran 3x
+// slower than its reduction launch.
+struct LaArgs {
+    const float *x;
+    const float *m;
+    int n;
+    float eps2;
+    int chunk;        // j per wave
+    int splits;       // S (grid.y)
+    float4 *partial;  // [S][n] when S > 1
+    int *ctr;         // [grid.x] tickets, zero between launches
+    float *a;
+    float *p;
+};
+
 template <int W>
-__global__ __launch_bounds__(W * 64) void forward_wsplit_kernel(FwdArgs P)
+__global__ __launch_bounds__(W * 64) void forward_la_kernel(LaArgs P)
 {
     __shared__ float4 tiles[W][64];
     __shared__ float4 red[W][64];
+    __shared__ int last;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int n = P.n;
     const float eps2 = P.eps2;
-    const int i = blockIdx.x * 64 + lane;
+    const int row0 = blockIdx.x * 64;
+    const int i = row0 + lane;
     const int ic = i < n ? i : n - 1;
     const float xi = P.x[3 * ic], yi = P.x[3 * ic + 1], zi = P.x[3 * ic + 2];
-    const int jb = wv * P.chunk;
+    const int64_t jb64 = ((int64_t)blockIdx.y * W + wv) * P.chunk;
+    const int jb = (int)min<int64_t>(jb64, n);
     const int je = min(n, jb + P.chunk);
-    const int row0 = blockIdx.x * 64;
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
     float4 *tile = tiles[wv];
     for (int t0 = jb; t0 < je; t0 += 64) {
         const int j = t0 + lane;
-        // Compiler-only barriers around the wave-private tile: the previous
-        // tile's reads finish before this write, and this write precedes the
-        // reads below (one wave's LDS accesses complete in issue order).
+        // wave-private tile: compiler-only barriers keep the previous tile's
+        // reads before this write and this write before the reads below
         __asm__ volatile("" ::: "memory");
         tile[lane] = (j < je) ? make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j])
                               : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -197,10 +224,10 @@ __global__ __launch_bounds__(W * 64) void forward_wsplit_kernel(FwdArgs P)
         const int cnt = min(64, je - t0);
         if (cnt == 64 && (t0 >= row0 + 64 || t0 + 64 <= row0)) {
 #pragma unroll 8
-            for (int s = 0; s < 64; ++s) pair_term(xi, yi, zi, tile[s], eps2, tx, ty, tz, tp);
+            for (int q = 0; q < 64; ++q) pair_term(xi, yi, zi, tile[q], eps2, tx, ty, tz, tp);
         } else {
-            for (int s = 0; s < cnt; ++s)
-                pair_term_masked(xi, yi, zi, tile[s], eps2, t0 + s == i, tx, ty, tz, tp);
+            for (int q = 0; q < cnt; ++q)
+                pair_term_masked(xi, yi, zi, tile[q], eps2, t0 + q == i, tx, ty, tz, tp);
         }
         ax += tx;
         ay += ty;
@@ -209,22 +236,60 @@ __global__ __launch_bounds__(W * 64) void forward_wsplit_kernel(FwdArgs P)
     }
     red[wv][lane] = make_float4(ax, ay, az, ap);
     __syncthreads();
-    if (wv == 0 && i < n) {
-        float4 s = red[0][lane];
+    if (P.splits == 1) {
+        if (wv == 0 && i < n) {
+            float4 t = red[0][lane];
+#pragma unroll
+            for (int w2 = 1; w2 < W; ++w2) {
+                const float4 q = red[w2][lane];
+                t.x += q.x;
+                t.y += q.y;
+                t.z += q.z;
+                t.w += q.w;
+            }
+            P.a[3 * i + 0] = t.x;
+            P.a[3 * i + 1] = t.y;
+            P.a[3 * i + 2] = t.z;
+            if (P.p) P.p[i] = t.w;
+        }
+        return;
+    }
+    if (wv == 0) {
+        float4 t = red[0][lane];
 #pragma unroll
         for (int w2 = 1; w2 < W; ++w2) {
             const float4 q = red[w2][lane];
-            s.x += q.x;
-            s.y += q.y;
-            s.z += q.z;
-            s.w += q.w;
+            t.x += q.x;
+            t.y += q.y;
+            t.z += q.z;
+            t.w += q.w;
         }
-        P.a[3 * i + 0] = s.x;
-        P.a[3 * i + 1] = s.y;
-        P.a[3 * i + 2] = s.z;
-        if (P.p) P.p[i] = s.w;
+        if (i < n) P.partial[(size_t)blockIdx.y * n + i] = t;
+        __threadfence();  // release the partial before taking a ticket
     }
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&P.ctr[blockIdx.x], 1) == P.splits - 1);
+    __syncthreads();
+    if (!last || wv != 0) return;
+    __threadfence();  // acquire every other split's partial
+    if (i < n) {
+        float4 t = P.partial[i];
+        for (int k = 1; k < P.splits; ++k) {
+            const float4 q = P.partial[(size_t)k * n + i];
+            t.x += q.x;
+            t.y += q.y;
+            t.z += q.z;
+            t.w += q.w;
+        }
+        P.a[3 * i + 0] = t.x;
+        P.a[3 * i + 1] = t.y;
+        P.a[3 * i + 2] = t.z;
+        if (P.p) P.p[i] = t.w;
+    }
+    if (lane == 0) atomicExch(&P.ctr[blockIdx.x], 0);
 }
+
+using LaFn = void (*)(LaArgs);
 
 using KernelFn = void (*)(FwdArgs);
 
@@ -236,13 +301,14 @@ struct Variant {
     int block, k, unroll;
     KernelFn direct, partial;
     int sym_w, sym_k, sym_occ;
-    int wsplit_w;  // > 0: single-launch gather with this many j-split waves
+    LaFn la;  // one-launch split gather (wave-split workgroups x S splits)
+    int la_w;
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, 0}
-#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, 0}
-#define FWD_WSPLIT_VARIANT(W) {"fwd_wsplit_w" #W, 64, 1, 0, forward_wsplit_kernel<W>, nullptr, 0, 0, 0, W}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0}
+#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -265,9 +331,9 @@ const Variant kVariants[] = {
     FWD_SYM_VARIANT(4, 4, 1),
     FWD_SYM_VARIANT(2, 8, 1),
     FWD_SYM_VARIANT(16, 4, 1),
-    FWD_WSPLIT_VARIANT(16),
-    FWD_WSPLIT_VARIANT(8),
-    FWD_WSPLIT_VARIANT(4),
+    FWD_LA_VARIANT(4),
+    FWD_LA_VARIANT(8),
+    FWD_LA_VARIANT(16),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -295,19 +361,15 @@ int forward_default_variant(int64_t n)
 {
     static const int gather_big = variant_index("fwd_b64_k1_u8");
     static const int gather_mid = variant_index("fwd_b256_k1_u8");
-    static const int wsplit_8 = variant_index("fwd_wsplit_w8");
-    static const int wsplit_16 = variant_index("fwd_wsplit_w16");
+    static const int one_launch = variant_index("fwd_la_w16");
     static const int pair_once_mid = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_big = variant_index("fwd_sym_w16_k4_o1");
     if (n > (1 << 21)) return gather_big;
     if (n >= (1 << 17)) return pair_once_big;
     if (n >= (1 << 15)) return pair_once_mid;
-    // The single-launch gather has one workgroup per 64 rows and so cannot
-    // balance row counts that are not near a multiple of the CU count; it
-    // serves only sizes where launch latency, not the pairs, sets the time.
-    if (n >= (1 << 12)) return gather_mid;
-    if (n >= (1 << 11)) return wsplit_16;
-    return wsplit_8;
+    if (n >= (1 << 13)) return gather_mid;
+    // Small n is set by launch latency: one launch, no reduction kernel.
+    return one_launch;
 }
 
 // Number of j-splits: enough workgroups to give every CU several, never a
@@ -326,14 +388,29 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          float eps2, float *a, float *p, hipStream_t stream)
 {
     const Variant &V = kVariants[variant];
-    if (V.wsplit_w) {
-        // j chunk per wave: a multiple of 64, every wave at least one tile
-        int chunk = (n + V.wsplit_w - 1) / V.wsplit_w;
-        chunk = (chunk + 63) / 64 * 64;
-        FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p};
+    if (V.la_w) {
+        // Waves per row block: about 4096 waves over the chip (4 per SIMD),
+        // at least 32 j per wave, at most n / 32 waves.
+        const int rb = (n + 63) / 64;
+        int per_rb = std::max(1, 4 * 4 * dev.num_cu / rb);
+        per_rb = std::min(per_rb, std::max(1, n / 32));
+        int splits = std::max(1, (per_rb + V.la_w / 2) / V.la_w);
+        const int waves = splits * V.la_w;
+        int chunk = (n + waves - 1) / waves;
+        chunk = chunk >= 64 ? (chunk + 63) / 64 * 64 : (chunk + 15) / 16 * 16;
+        splits = std::max(1, (int)(((int64_t)n + (int64_t)chunk * V.la_w - 1) / ((int64_t)chunk * V.la_w)));
+        LaArgs P{x, m, n, eps2, chunk, splits, nullptr, nullptr, a, p};
+        if (splits > 1) {
+            void *ws = nullptr;
+            nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
+            if (st != NBODY_OK) return st;
+            P.partial = static_cast<float4 *>(ws);
+            st = counters(dev, stream, (size_t)rb, &P.ctr);
+            if (st != NBODY_OK) return st;
+        }
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
         prof_mark(stream, 0);
-        hipLaunchKernelGGL(V.direct, dim3((n + 63) / 64), dim3(V.wsplit_w * 64), 0, stream, P);
+        hipLaunchKernelGGL(V.la, dim3(rb, splits), dim3(V.la_w * 64), 0, stream, P);
         prof_mark(stream, 1);
         return check_launch(V.name);
     }
