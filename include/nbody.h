@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 1
+#define NBODY_ABI_VERSION 2
 #define NBODY_MAX_N (INT64_C(1) << 28)
 
 typedef enum nbody_status {
@@ -82,8 +82,9 @@ const char *nbody_last_error(void);
  * library workspace above 2^17 particles (2.1 GB at n = 2^20).  Outside that range the default
  * gathers every ordered pair per row with j-splits: below 2^13 in one launch
  * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
- * workspace and one int counter per 64 rows), otherwise with a reduction
- * launch (at most 16 n * splits bytes).
+ * workspace and one int counter per 64 rows), otherwise with float64 row
+ * sums (as NBODY_FORCES_F64_SUM below) and a reduction launch (at most
+ * 32 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
  *
@@ -95,6 +96,29 @@ const char *nbody_last_error(void);
  */
 nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
                           float *a, float *p, void *stream);
+
+/* Flag bits of nbody_forces_ex. */
+#define NBODY_FORCES_F64_SUM 1u
+
+/*
+ * nbody_forces with option flags; nbody_forces(...) is
+ * nbody_forces_ex(..., 0u, stream).  Same sum, arguments, layouts, ownership
+ * and errors as nbody_forces.
+ *
+ * NBODY_FORCES_F64_SUM: keep each row's running sum in float64.  The pair
+ * terms and each j-tile's sum (64 to 256 terms) stay float32; the tile
+ * sums, and the j-split partials, are added in float64 and rounded to
+ * float32 once at the store.  Float32 running sums add n / tile tile sums in
+ * float32, an error that grows with n; the paper computes in single
+ * precision throughout (Sec. IV).  The default already sums in float64
+ * outside 2^15 <= n <= 2^21; inside that range the flag trades the
+ * pair-once kernel for the row gather (about 20% slower at n = 2^20) and
+ * 32 n * splits bytes of workspace.  A forced variant (nbody_set_variant)
+ * is honoured only if it is one of the "_f64sum" variants.
+ * Errors: as nbody_forces; unknown flag bits -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float eps2,
+                             float *a, float *p, uint32_t flags, void *stream);
 
 /*
  * Backward (vector-Jacobian product) of nbody_forces, derived from

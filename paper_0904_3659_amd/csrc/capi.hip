@@ -411,7 +411,16 @@ const char *nbody_last_error(void) { return nbody::last_error_cstr(); }
 nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2, float *a,
                           float *p, void *stream)
 {
+    return nbody_forces_ex(x, m, n, eps2, a, p, 0u, stream);
+}
+
+nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float eps2, float *a,
+                             float *p, uint32_t flags, void *stream)
+{
     clear_error();
+    if (flags & ~(uint32_t)NBODY_FORCES_F64_SUM)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
+                    (unsigned)(flags & ~(uint32_t)NBODY_FORCES_F64_SUM));
     if (n < 0 || n > NBODY_MAX_N)
         return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld outside [0, %lld]", (long long)n,
                     (long long)NBODY_MAX_N);
@@ -425,8 +434,12 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
     Device dev;
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
-    st = forward_run(select_variant(NBODY_KIND_FORWARD, n), dev, x, m, (int)n, eps2, a, p,
-                     (hipStream_t)stream);
+    int variant = select_variant(NBODY_KIND_FORWARD, n);
+    if ((flags & NBODY_FORCES_F64_SUM) && !forward_variant_f64sum(variant)) {
+        const int forced = forced_variant(NBODY_KIND_FORWARD);
+        variant = forward_variant_f64sum(forced) ? forced : forward_default_f64sum_variant(n);
+    }
+    st = forward_run(variant, dev, x, m, (int)n, eps2, a, p, (hipStream_t)stream);
     if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
     return st;
 }

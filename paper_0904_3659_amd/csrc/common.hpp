@@ -64,6 +64,8 @@ void record_tuned_variant(int kind, int64_t n, int index);
 int forward_variant_count();
 const char *forward_variant_name(int index);
 int forward_default_variant(int64_t n);
+bool forward_variant_f64sum(int variant);
+int forward_default_f64sum_variant(int64_t n);
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m,
                          int n, float eps2, float *a, float *p, hipStream_t stream);
 

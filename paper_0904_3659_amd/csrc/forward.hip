@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 namespace nbody {
 namespace {
@@ -43,11 +44,19 @@ struct FwdArgs {
     float4 *partial;  // [splits][n] when PARTIAL
     float *a;
     float *p;
+    double *partial_d;  // [splits][n][4] when PARTIAL and D64
 };
 
-template <int BLOCK, int K, int U, bool PARTIAL>
+// D64: the running sums of every row are float64; each j-tile's float32
+// partial is widened and added once per tile, and split partials are kept
+// and added in float64.  Only the float32 sums inside one tile remain, so
+// the rounding error no longer grows with the number of tiles (n / BLOCK).
+// About 8 float64 VALU operations per row per tile: under 1% of the pair
+// work at BLOCK = 64.
+template <int BLOCK, int K, int U, bool PARTIAL, bool D64 = false>
 __global__ __launch_bounds__(BLOCK) void forward_kernel(FwdArgs P)
 {
+    using Acc = typename std::conditional<D64, double, float>::type;
     constexpr int TILE = BLOCK;
     __shared__ float4 tile[TILE];
 
@@ -69,9 +78,9 @@ __global__ __launch_bounds__(BLOCK) void forward_kernel(FwdArgs P)
         yi[k] = P.x[3 * ic + 1];
         zi[k] = P.x[3 * ic + 2];
     }
-    float ax[K], ay[K], az[K], pp[K];
+    Acc ax[K], ay[K], az[K], pp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ax[k] = ay[k] = az[k] = pp[k] = 0.0f;
+    for (int k = 0; k < K; ++k) ax[k] = ay[k] = az[k] = pp[k] = Acc(0);
 
     // j-tile prefetch registers
     float4 next = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -119,10 +128,10 @@ __global__ __launch_bounds__(BLOCK) void forward_kernel(FwdArgs P)
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            ax[k] += tx[k];
-            ay[k] += ty[k];
-            az[k] += tz[k];
-            pp[k] += tp[k];
+            ax[k] += Acc(tx[k]);
+            ay[k] += Acc(ty[k]);
+            az[k] += Acc(tz[k]);
+            pp[k] += Acc(tp[k]);
         }
     }
 
@@ -130,13 +139,18 @@ __global__ __launch_bounds__(BLOCK) void forward_kernel(FwdArgs P)
     for (int k = 0; k < K; ++k) {
         const int i = ii[k];
         if (i >= n) continue;
-        if (PARTIAL) {
-            P.partial[(size_t)blockIdx.y * n + i] = make_float4(ax[k], ay[k], az[k], pp[k]);
+        if (PARTIAL && D64) {
+            double2 *q = reinterpret_cast<double2 *>(P.partial_d + ((size_t)blockIdx.y * n + i) * 4);
+            q[0] = make_double2(ax[k], ay[k]);
+            q[1] = make_double2(az[k], pp[k]);
+        } else if (PARTIAL) {
+            P.partial[(size_t)blockIdx.y * n + i] =
+                make_float4((float)ax[k], (float)ay[k], (float)az[k], (float)pp[k]);
         } else {
-            P.a[3 * i + 0] = ax[k];
-            P.a[3 * i + 1] = ay[k];
-            P.a[3 * i + 2] = az[k];
-            if (P.p) P.p[i] = pp[k];
+            P.a[3 * i + 0] = (float)ax[k];
+            P.a[3 * i + 1] = (float)ay[k];
+            P.a[3 * i + 2] = (float)az[k];
+            if (P.p) P.p[i] = (float)pp[k];
         }
     }
 }
@@ -159,6 +173,28 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float4 *__rest
     a[3 * i + 1] = s.y;
     a[3 * i + 2] = s.z;
     if (p) p[i] = s.w;
+}
+
+// The float64 form of reduce_splits_kernel (partials of D64 kernels).
+__global__ __launch_bounds__(256) void reduce_splits_d_kernel(const double *__restrict__ partial,
+                                                              int splits, int n, float *a, float *p)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double2 *q = reinterpret_cast<const double2 *>(partial);
+    double2 s0 = q[2 * (size_t)i], s1 = q[2 * (size_t)i + 1];
+    for (int k = 1; k < splits; ++k) {
+        const size_t e = 2 * ((size_t)k * n + i);
+        const double2 t0 = q[e], t1 = q[e + 1];
+        s0.x += t0.x;
+        s0.y += t0.y;
+        s1.x += t1.x;
+        s1.y += t1.y;
+    }
+    a[3 * i + 0] = (float)s0.x;
+    a[3 * i + 1] = (float)s0.y;
+    a[3 * i + 2] = (float)s1.x;
+    if (p) p[i] = (float)s1.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -303,12 +339,16 @@ struct Variant {
     int sym_w, sym_k, sym_occ;
     LaFn la;  // one-launch split gather (wave-split workgroups x S splits)
     int la_w;
+    bool d64;  // float64 running sums (forward_kernel's D64)
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0}
-#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0}
-#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0, false}
+#define FWD_D64_VARIANT(B, K, U)                                                               \
+    {"fwd_b" #B "_k" #K "_u" #U "_f64sum", B, K, U, forward_kernel<B, K, U, false, true>,      \
+     forward_kernel<B, K, U, true, true>, 0, 0, 0, nullptr, 0, true}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0, false}
+#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -334,6 +374,10 @@ const Variant kVariants[] = {
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
+    // float64 running sums, for accuracy at very large n
+    FWD_D64_VARIANT(256, 1, 8),
+    FWD_D64_VARIANT(64, 1, 8),
+    FWD_D64_VARIANT(128, 2, 8),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -359,8 +403,10 @@ static int variant_index(const char *name)
 // gather kernel, which needs no workspace at that size, takes over.
 int forward_default_variant(int64_t n)
 {
-    static const int gather_big = variant_index("fwd_b64_k1_u8");
-    static const int gather_mid = variant_index("fwd_b256_k1_u8");
+    // The gathers keep float64 row sums: as fast as float32 sums here and
+    // 10-100x more accurate above a million bodies.
+    static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
+    static const int gather_mid = variant_index("fwd_b256_k1_u8_f64sum");
     static const int one_launch = variant_index("fwd_la_w16");
     static const int pair_once_mid = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_big = variant_index("fwd_sym_w16_k4_o1");
@@ -370,6 +416,15 @@ int forward_default_variant(int64_t n)
     if (n >= (1 << 13)) return gather_mid;
     // Small n is set by launch latency: one launch, no reduction kernel.
     return one_launch;
+}
+
+bool forward_variant_f64sum(int v) { return v >= 0 && v < kNumVariants && kVariants[v].d64; }
+
+int forward_default_f64sum_variant(int64_t n)
+{
+    static const int big = variant_index("fwd_b64_k1_u8_f64sum");
+    static const int mid = variant_index("fwd_b256_k1_u8_f64sum");
+    return n > (1 << 17) ? big : mid;
 }
 
 // Number of j-splits: enough workgroups to give every CU several, never a
@@ -423,7 +478,7 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
     chunk = (chunk + V.block - 1) / V.block * V.block;
     splits = (n + chunk - 1) / chunk;
 
-    FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p};
+    FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p, nullptr};
     if (splits == 1) {
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
         prof_mark(stream, 0);
@@ -432,17 +487,25 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
         return check_launch(V.name);
     }
     void *ws = nullptr;
-    nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
+    const size_t entry = V.d64 ? 4 * sizeof(double) : sizeof(float4);
+    nbody_status st = workspace(dev, stream, entry * (size_t)splits * n, &ws);
     if (st != NBODY_OK) return st;
-    P.partial = static_cast<float4 *>(ws);
+    if (V.d64)
+        P.partial_d = static_cast<double *>(ws);
+    else
+        P.partial = static_cast<float4 *>(ws);
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
     prof_mark(stream, 0);
     hipLaunchKernelGGL(V.partial, dim3(iblocks, splits), dim3(V.block), 0, stream, P);
     prof_mark(stream, 1);
     st = check_launch(V.name);
     if (st != NBODY_OK) return st;
-    hipLaunchKernelGGL(reduce_splits_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
-                       P.partial, splits, n, a, p);
+    if (V.d64)
+        hipLaunchKernelGGL(reduce_splits_d_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           P.partial_d, splits, n, a, p);
+    else
+        hipLaunchKernelGGL(reduce_splits_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           P.partial, splits, n, a, p);
     return check_launch("reduce_splits");
 }
 

@@ -162,6 +162,14 @@ def plummer_1m_lognormal(n: int = 1 << 20, rows: int = 4096) -> Workload:
                     rows=check_rows(n, rows, (3, 2)))
 
 
+def plummer_4m_lognormal(rows: int = 1024) -> Workload:
+    """N = 2^22 Plummer sphere, log-normal (sigma 1) masses summing to 1,
+    eps^2 = 1e-6, with ``rows`` seeded check rows (float32 growth study)."""
+    n = 1 << 22
+    return Workload(f"plummer_n{n}_lognormal_eps2_1e-6", plummer_positions(n, (7, 0)),
+                    lognormal_masses(n, (7, 1)), 1e-6, rows=check_rows(n, rows, (7, 2)))
+
+
 def adjoint_16k(n: int = 16384) -> Workload:
     """N = 16,384 Plummer sphere with log-normal masses and eps^2 = 1e-4.
 

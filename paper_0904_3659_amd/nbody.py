@@ -19,7 +19,7 @@ import torch
 from . import build as _build
 
 FORWARD, BACKWARD, BATCHED = 0, 1, 2
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _STATUS = {
     0: "NBODY_OK",
@@ -57,6 +57,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_status_string.argtypes = [ctypes.c_int]
         L.nbody_last_error.restype = ctypes.c_char_p
         L.nbody_forces.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp]
+        L.nbody_forces_ex.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, ctypes.c_uint32, _vp]
         L.nbody_forces_backward.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp, _vp, _vp]
         L.nbody_forces_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp, _vp, _vp]
         L.nbody_axpy.argtypes = [_vp, _vp, _i64, _f32, _vp]
@@ -73,7 +74,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(ctypes.c_int)]
         L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
         L.nbody_selected_variant.restype = ctypes.c_int
-        for f in ("nbody_forces", "nbody_forces_backward", "nbody_forces_batched", "nbody_axpy",
+        for f in ("nbody_forces", "nbody_forces_ex", "nbody_forces_backward", "nbody_forces_batched",
+                  "nbody_axpy",
                   "nbody_kick_drift",
                   "nbody_set_variant", "nbody_autotune", "nbody_release_workspace",
                   "nbody_profile_enable", "nbody_profile_read"):
@@ -121,11 +123,16 @@ def _eps2(eps2) -> float:
 
 # ---------------------------------------------------------------- evaluation
 
-def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential: bool = True):
+F64_SUM = 1  # NBODY_FORCES_F64_SUM
+
+
+def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential: bool = True,
+           f64_sum: bool = False):
     """Eq. (gravity): (a [n,3], p [n]) in the paper's sign, j != i.
 
     ``out`` may supply preallocated (a, p).  With ``potential=False`` the
-    potential is not stored and ``p`` is returned as None.
+    potential is not stored and ``p`` is returned as None.  ``f64_sum`` keeps
+    each row's running sum (over j-tiles and j-splits) in float64.
     """
     n = int(x.shape[0]) if x.dim() == 2 else -1
     _want(x, "x", (n, 3))
@@ -140,7 +147,12 @@ def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential
         if p is not None:
             _want(p, "p", (n,), dev)
     with torch.cuda.device(dev):
-        _check(lib().nbody_forces(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p), _stream(dev)))
+        if f64_sum:
+            _check(lib().nbody_forces_ex(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p),
+                                         F64_SUM, _stream(dev)))
+        else:
+            _check(lib().nbody_forces(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p),
+                                      _stream(dev)))
     return a, p
 
 

@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.nbody_abi_version() == 1
+    assert L.nbody_abi_version() == 2
     for code, name in enumerate(["NBODY_OK", "NBODY_ERROR_INVALID_ARGUMENT",
                                  "NBODY_ERROR_UNSUPPORTED_DEVICE", "NBODY_ERROR_OUT_OF_MEMORY",
                                  "NBODY_ERROR_LAUNCH_FAILED", "NBODY_ERROR_INTERNAL"]):
@@ -86,6 +86,17 @@ def test_forward_validation(L):
     # n == 0 is a no-op that succeeds without touching the device
     assert L.nbody_forces(None, None, 0, 1e-4, None, None, None) == 0
     assert L.nbody_last_error() == b""
+
+
+def test_forward_ex_validation(L):
+    L.nbody_forces_ex.argtypes = [vp, vp, i64, f32, vp, vp, ctypes.c_uint32, vp]
+    assert L.nbody_forces_ex(FAKE, FAKE, 4, 1e-4, FAKE, None, 2, None) == 1
+    assert b"flag" in L.nbody_last_error()
+    assert L.nbody_forces_ex(FAKE, FAKE, 4, -1.0, FAKE, None, 1, None) == 1
+    assert L.nbody_forces_ex(FAKE, FAKE, -1, 1e-4, FAKE, None, 1, None) == 1
+    assert L.nbody_forces_ex(None, None, 0, 1e-4, None, None, 1, None) == 0
+    names = [L.nbody_variant_name(0, k).decode() for k in range(L.nbody_variant_count(0))]
+    assert any(nm.endswith("_f64sum") for nm in names)
 
 
 def test_backward_validation(L):

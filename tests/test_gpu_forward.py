@@ -274,3 +274,29 @@ def test_one_launch_split_gather(nb, n):
             assert_parity(host(a3), host(p3), ar3, pr3, label=f"{name} n=333 after n={n}")
     finally:
         nb.set_variant(nb.FORWARD, -1)
+
+
+def test_f64_sum_at_four_million(nb):
+    # float64 row sums remove the growth of the float32 error with the number
+    # of j-tiles: at n = 2^22 the float32-sum gather errs ~1e-5 and the
+    # float64-sum one ~1e-7 (the pair terms themselves stay float32)
+    dev = need_gpu()
+    w = inputs.plummer_4m_lognormal()
+    ar, pr = R.forces_rows(w.x, w.m, w.eps2, w.rows)
+    x, m = to_dev(w.x, dev), to_dev(w.m, dev)
+    names = nb.variant_names(nb.FORWARD)
+    try:
+        nb.set_variant(nb.FORWARD, names.index("fwd_b64_k1_u8"))
+        a32, p32 = nb.forces(x, m, w.eps2)
+        nb.set_variant(nb.FORWARD, -1)
+        a64, p64 = nb.forces(x, m, w.eps2, f64_sum=True)
+        assert names[nb.selected_variant(nb.FORWARD, w.n)].endswith("_f64sum")
+        a_def, p_def = nb.forces(x, m, w.eps2)
+        assert torch.equal(a_def, a64) and torch.equal(p_def, p64)
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
+    e32 = errors(host(a32)[w.rows], host(p32)[w.rows], ar, pr)
+    e64 = errors(host(a64)[w.rows], host(p64)[w.rows], ar, pr)
+    print(f"[parity] {w.name} float32 sums {e32}  float64 sums {e64}", flush=True)
+    assert max(e64) <= 1e-6
+    assert max(e64) * 10 <= max(e32)
