@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-interactions/s & % FP32 VALU peak (38 flop/pair): fwd, adjoint, batched"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_plummer_n1048576_traffic.txt")
 FORWARD_SOURCES = [os.path.join(ROOT, "paper_0904_3659_amd", "csrc", f)
-                   for f in ("forward_sym.hip", "pair_once.hpp", "common.hpp")]
+                   for f in ("forward_sym.hip", "pair_once.hpp", "pair_term.hpp")]
 
 
 def log(msg: str) -> None:
@@ -98,9 +98,60 @@ def cpu_baseline(w, budget_s: float = 12.0):
         done += part.size
         chunk = min(chunk * 2, 8192)
     pairs = done * (n - 1)
-    return {"value": pairs / spent, "unit": "pair-interactions/s", "cores": R.num_threads(),
+    threads = R.num_threads()
+    # the same oracle on one thread (the paper's cpu-only program ran on one
+    # core, Sec. V-A): the first rows of the same sample for about 3 s
+    R.set_num_threads(1)
+    try:
+        done1, spent1 = 0, 0.0
+        while done1 < rows.size and spent1 < 3.0:
+            part = rows[done1:done1 + 64]
+            t0 = time.perf_counter()
+            R.forces_rows(w.x, w.m, w.eps2, part)
+            spent1 += time.perf_counter() - t0
+            done1 += part.size
+    finally:
+        R.set_num_threads(threads)
+    return {"value": pairs / spent, "unit": "pair-interactions/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{done} seeded rows x {n - 1} j of {w.name}, FP64, {spent:.2f} s"}
+            "sample": f"{done} seeded rows x {n - 1} j of {w.name}, FP64, {spent:.2f} s",
+            "single_thread_value": done1 * (n - 1) / spent1,
+            "single_thread_sample": f"first {done1} of the same rows, 1 thread, {spent1:.2f} s"}
+
+
+def graph_plain_ms(plain, ab, pb, torch):
+    """The per-system launches captured once in a HIP graph and replayed: a
+    stronger baseline than launching them from Python.  The replay must
+    reproduce the eager result bitwise, else None is reported."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plain()                      # grows the library's workspace for s
+    s.synchronize()
+    ref_a, ref_p = ab.clone(), pb.clone()
+    g = torch.cuda.CUDAGraph()
+    try:
+        with torch.cuda.graph(g, stream=s):
+            plain()
+    except RuntimeError as e:
+        log(f"graph capture failed: {e}")
+        return None
+    torch.cuda.synchronize()
+    ab.zero_()
+    pb.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    if not (torch.equal(ab, ref_a) and torch.equal(pb, ref_p)):
+        log("graph replay differs from the eager launches")
+        return None
+    t0 = time.perf_counter()
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 5
+    ok = torch.equal(ab, ref_a) and torch.equal(pb, ref_p)
+    del g
+    return ms if ok else None
 
 
 def main() -> int:
@@ -279,6 +330,7 @@ def main() -> int:
         plain()
         torch.cuda.synchronize()
         wall_plain = time.perf_counter() - t0
+        graph_ms = graph_plain_ms(plain, ab, pb, torch)
         pb_pairs = metrics.pairs_ensemble(ens.sizes())
         out["batched"] = {
             "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
@@ -287,6 +339,8 @@ def main() -> int:
             "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
             "plain_launches_ms": wall_plain * 1e3,
             "speedup_vs_plain": wall_plain * 1e3 / kb,
+            "graph_plain_launches_ms": graph_ms,
+            "speedup_vs_graph": (graph_ms / kb) if graph_ms else None,
             "plan_build_s": plan_s,
             "variant": nb.variant_names(nb.BATCHED)[nb.selected_variant(nb.BATCHED, int(np.mean(ens.sizes())))],
         }

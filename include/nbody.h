@@ -19,6 +19,16 @@
  *   until nbody_release_workspace() or process exit.  Calls that share one
  *   stream reuse it safely; calls on different streams use different
  *   workspaces.
+ * - HIP graph capture: nbody_forces, nbody_forces_ex, nbody_forces_backward,
+ *   nbody_forces_batched, nbody_axpy and nbody_kick_drift may be captured on
+ *   a stream once the same call has run eagerly on that stream (so that the
+ *   stream's workspace, counters and the batched plan exist; a first call
+ *   allocates and a first batched call synchronises, which capture forbids).
+ *   The graph keeps the workspace addresses of that stream: while it may
+ *   replay, make no call on that stream that needs a larger workspace, do
+ *   not call nbody_release_workspace(), and keep the number of distinct
+ *   batched offset sets below the plan cache size (8).  No memset is
+ *   recorded: counters are cleared by the kernels that use them.
  * - No C++ exception crosses this interface.  Every call returns a status;
  *   on failure nbody_last_error() gives a thread-local detail string.
  *   Argument checks run before any HIP call, so an invalid call touches no

@@ -30,6 +30,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Thread count for later calls (timing only: results do not depend on it). */
+void oracle_set_num_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
 /*
  * Eq. (gravity), Sec. I.  For each requested row i:
  *     a_i = sum_{j != i} m_j (x_i - x_j) / (|x_i - x_j|^2 + eps^2)^(3/2)

@@ -34,6 +34,8 @@ def configure(L: ctypes.CDLL) -> ctypes.CDLL:
     """Declare the C signatures on a loaded copy of the reference library."""
     i64, dbl = ctypes.c_int64, ctypes.c_double
     L.oracle_num_threads.restype = ctypes.c_int
+    L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    L.oracle_set_num_threads.restype = None
     L.oracle_forces_rows.argtypes = [_dptr, _dptr, i64, dbl, _i64ptr, i64, _dptr, _dptr]
     L.oracle_forces.argtypes = [_dptr, _dptr, i64, dbl, _dptr, _dptr]
     L.oracle_forces_batched.argtypes = [_i64ptr, i64, _dptr, _dptr, dbl, _dptr, _dptr]
@@ -57,6 +59,11 @@ def lib() -> ctypes.CDLL:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(threads: int) -> None:
+    """OpenMP threads for later calls; the results do not depend on it."""
+    lib().oracle_set_num_threads(int(threads))
 
 
 def _d(a, shape=None) -> np.ndarray:
