@@ -16,6 +16,7 @@
 // row count alone cannot fill the device; per-tile partial sums folded into
 // the running sums (two-level accumulation).  No atomics.
 #include "common.hpp"
+#include "pair_once.hpp"
 
 #include <cstring>
 
@@ -254,11 +255,6 @@ struct SymBwdArgs {
     float4 *partial;  // [C + M/2][n]: (dL/dx, dL/dm)
 };
 
-__device__ __forceinline__ int bwd_ring_len(int I, int M)
-{
-    return (M - 1) / 2 + (((M & 1) == 0 && I < M / 2) ? 1 : 0);
-}
-
 // One unordered pair: adds F and the k mass term to tk; returns the j-side
 // contributions (-F, j mass term) through jx..jm.
 __device__ __forceinline__ void adj_pair_once(const float4 &xk, const float4 &wk, const float4 &q,
@@ -422,7 +418,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 
     // this chunk's share of the block's tiles (diagonal first, then the ring
     // delta-major); all-padding tiles are skipped (uniform)
-    const int U = TPB + bwd_ring_len(I, M) * TPB;
+    const int U = TPB + ring_len(I, M) * TPB;
     const int u0 = (int)((long long)U * c / C);
     const int u1 = (int)((long long)U * (c + 1) / C);
     auto base_of = [&](int u, int &delta) {
@@ -518,29 +514,6 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         if (kk[k] < n) A.partial[(size_t)c * n + kk[k]] = acc[k];
 }
 
-template <int PB>
-__global__ __launch_bounds__(256) void backward_sym_reduce_kernel(const float4 *__restrict__ partial,
-                                                                  int n, int M, int C, float *gx,
-                                                                  float *gm)
-{
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const int J = j / PB;
-    const int H = (M - 1) / 2 + (((M & 1) == 0 && J >= M / 2) ? 1 : 0);
-    float4 s = partial[j];
-    for (int k = 1; k < C + H; ++k) {
-        const float4 q = partial[(size_t)k * n + j];
-        s.x += q.x;
-        s.y += q.y;
-        s.z += q.z;
-        s.w += q.w;
-    }
-    gx[3 * j + 0] = s.x;
-    gx[3 * j + 1] = s.y;
-    gx[3 * j + 2] = s.z;
-    if (gm) gm[j] = s.w;
-}
-
 // OCC divides the chunk count (as in the pair-once forward kernel).
 template <int W, int K, int OCC>
 nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
@@ -569,9 +542,9 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
-    hipLaunchKernelGGL((backward_sym_reduce_kernel<PB>), dim3((n + 255) / 256), dim3(256), 0,
-                       stream, A.partial, n, M, C, gx, gm);
-    return check_launch("backward_sym_reduce");
+    hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
+                       A.partial, n, M, C, gx, gm);
+    return check_launch("slot_reduce");
 }
 
 using KernelFn = void (*)(BwdArgs);
@@ -605,6 +578,9 @@ const Variant kVariants[] = {
     BWD_SYM_VARIANT(4, 2, 2),
     BWD_SYM_VARIANT(8, 4, 1),
     BWD_SYM_VARIANT(16, 2, 1),
+    BWD_SYM_VARIANT(4, 1, 1),
+    BWD_SYM_VARIANT(2, 2, 1),
+    BWD_SYM_VARIANT(2, 4, 1),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

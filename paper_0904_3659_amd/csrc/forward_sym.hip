@@ -27,30 +27,6 @@ __global__ __launch_bounds__(W * 64) void forward_sym_kernel(SymArgs A)
     pair_once_block<W, K>(A.x, A.m, A.n, A.eps2, A.M, I, c, A.C, A.partial, tile, jacc);
 }
 
-// a_j, p_j = i-side chunk slots + the j-side slots the particle's block
-// received, added in slot order.
-template <int PB>
-__global__ __launch_bounds__(256) void forward_sym_reduce_kernel(const float4 *__restrict__ partial,
-                                                                 int n, int M, int C, float *a,
-                                                                 float *p)
-{
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const int H = ring_in(j / PB, M);
-    float4 s = partial[j];
-    for (int k = 1; k < C + H; ++k) {
-        const float4 q = partial[(size_t)k * n + j];
-        s.x += q.x;
-        s.y += q.y;
-        s.z += q.z;
-        s.w += q.w;
-    }
-    a[3 * j + 0] = s.x;
-    a[3 * j + 1] = s.y;
-    a[3 * j + 2] = s.z;
-    if (p) p[j] = s.w;
-}
-
 // OCC divides the chunk count: 1 fills every resident workgroup slot once;
 // 2 gives half as many, twice as long workgroups (fewer partial slots, less
 // tail imbalance at small n, lower occupancy).
@@ -82,9 +58,9 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
-    hipLaunchKernelGGL((forward_sym_reduce_kernel<PB>), dim3((n + 255) / 256), dim3(256), 0, stream,
+    hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
                        A.partial, n, M, C, a, p);
-    return check_launch("forward_sym_reduce");
+    return check_launch("slot_reduce");
 }
 
 }  // namespace

@@ -61,6 +61,54 @@ __host__ __device__ __forceinline__ int ring_in(int J, int M)
     return (M - 1) / 2 + (((M & 1) == 0 && J >= M / 2) ? 1 : 0);
 }
 
+// Final sum of the pair-once kernels: particle j's output is the sum of its
+// C chunk slots and the ring_in(J, M) j-side slots its block J received
+// (partial[k][j], k < C + ring_in).  Four groups of 64 threads each add a
+// contiguous quarter of the slots in slot order, and the four group sums are
+// added in group order: a fixed order (bitwise reproducible) with four times
+// the parallelism of one thread per particle.  xyz goes to out3[j][3], w to
+// out1[j] (skipped when out1 is NULL).  A workgroup covers 64 particles.
+template <int PB>
+__global__ __launch_bounds__(256) void slot_reduce_kernel(const float4 *__restrict__ partial,
+                                                          int n, int M, int C, float *out3,
+                                                          float *out1)
+{
+    __shared__ float4 red[4][64];
+    const int l = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + l;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < n) {
+        const int S = C + ring_in(j / PB, M);
+        const int q = (S + 3) / 4;
+        const int k1 = min(S, (g + 1) * q);
+#pragma unroll 4
+        for (int k = g * q; k < k1; ++k) {
+            const float4 v = partial[(size_t)k * n + j];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+    }
+    red[g][l] = s;
+    __syncthreads();
+    if (g != 0 || j >= n) return;
+    float4 t = red[0][l];
+#pragma unroll
+    for (int g2 = 1; g2 < 4; ++g2) {
+        const float4 v = red[g2][l];
+        t.x += v.x;
+        t.y += v.y;
+        t.z += v.z;
+        t.w += v.w;
+    }
+    out3[3 * j + 0] = t.x;
+    out3[3 * j + 1] = t.y;
+    out3[3 * j + 2] = t.z;
+    if (out1) out1[j] = t.w;
+}
+
 // Tile u of block I's sequence: the TPB diagonal tiles (delta 0), then the
 // ring tiles delta-major.  Returns the first particle index of the tile.
 template <int PB>
