@@ -286,20 +286,28 @@ def main() -> int:
         mm = torch.from_numpy(wa.m).to(dev).requires_grad_(True)
         u = torch.from_numpy(wa.extra["u"]).to(dev)
 
-        def lf():
-            xT, _ = nb.leapfrog(x0, v0, mm, wa.eps2, 1e-3, 64, checkpoint_every=8)
+        def lf(graphs):
+            xT, _ = nb.leapfrog(x0, v0, mm, wa.eps2, 1e-3, 64, checkpoint_every=8, graphs=graphs)
             torch.autograd.grad((xT * u).sum(), (x0, v0, mm))
 
-        lf()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lf()
-        torch.cuda.synchronize()
-        lf_s = time.perf_counter() - t0
-        # 65 + 8 recomputed force evaluations, 64 VJPs
+        lf_times = {}
+        for graphs in (False, True):
+            lf(graphs)                   # the first graphs call captures them
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                lf(graphs)
+            torch.cuda.synchronize()
+            lf_times[graphs] = (time.perf_counter() - t0) / 3
+        lf_s = lf_times[True]
+        # forward: a(x0) and one force evaluation per step; reverse: every
+        # segment but the last (whose positions the forward pass kept) is
+        # recomputed from its checkpoint (x, v, a): 7 x 8 evaluations
+        f_evals = 1 + 64 + 7 * 8
         out["leapfrog_grad"] = {"workload": wa.name + "_64steps_dt1e-3_ckpt8", "seconds": lf_s,
-                                "force_evals": 73, "vjp_evals": 64,
-                                "pairs_per_s": (73 + 64) * pa / lf_s}
+                                "seconds_without_graphs": lf_times[False],
+                                "force_evals": f_evals, "vjp_evals": 64,
+                                "pairs_per_s": (f_evals + 64) * pa / lf_s}
         log(f"leap-frog gradient {lf_s * 1e3:.1f} ms")
 
         # ------------------------------------------------------ batched

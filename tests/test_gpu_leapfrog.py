@@ -118,7 +118,7 @@ def test_resume_from_checkpoint_is_bitwise(nb):
     x, v, m, _ = _case(3000, 5)
     xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
     x_full, v_full, saved = LF.integrate(xt, vt, mt, 1e-4, 2e-3, 40, keep_every=8)
-    xs, vs = saved[24]
+    xs, vs, _ = saved[24]
     x_res, v_res, _ = LF.integrate(xs, vs, mt, 1e-4, 2e-3, 16)
     assert torch.equal(x_res, x_full) and torch.equal(v_res, v_full)
 
@@ -133,3 +133,26 @@ def test_kick_drift_matches_two_axpys(nb):
     nb.axpy_(v2, a, -0.0125)
     nb.axpy_(x2, v2, 0.025)
     assert torch.equal(x1, x2) and torch.equal(v1, v2)
+
+
+@pytest.mark.parametrize("n,steps,k", [(1000, 20, 8), (2048, 64, 8), (40000, 16, 4)])
+def test_graph_replay_equals_eager(nb, n, steps, k):
+    # HIP-graph segments (forward k steps, position recomputation, interior
+    # reverse sweep) against the eager launches: bitwise, for a loss on both
+    # x_T and v_T, a ragged last segment (20 = 2 x 8 + 4) and the one-launch,
+    # split-gather and pair-once force kernels
+    dev = need_gpu()
+    x, v, m, u = _case(n, 6)
+    uv = inputs.normal(x.shape, (73, n))
+    res = []
+    for graphs in (False, True, True):           # the second graphs run reuses the cache
+        xt = to_dev(x, dev).requires_grad_(True)
+        vt = to_dev(v, dev).requires_grad_(True)
+        mt = to_dev(m, dev).requires_grad_(True)
+        xT, vT = nb.leapfrog(xt, vt, mt, 1e-4, 1e-3, steps, checkpoint_every=k, graphs=graphs)
+        ((xT * to_dev(u, dev)).sum() + (vT * to_dev(uv, dev)).sum()).backward()
+        torch.cuda.synchronize()
+        res.append((xT.detach(), vT.detach(), xt.grad, vt.grad, mt.grad))
+    for got in res[1:]:
+        for a, b in zip(res[0], got):
+            assert torch.equal(a, b)
