@@ -88,8 +88,9 @@ const char *nbody_last_error(void);
  * The result is bitwise reproducible for a fixed n, variant and device.
  * Kernels: for 2^15 <= n <= 2^21 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
- * force is antisymmetric in the pair); it needs about 8 n^2 / 4096 bytes of
- * library workspace above 2^17 particles (2.1 GB at n = 2^20).  Outside that range the default
+ * force is antisymmetric in the pair); it needs about 8 n^2 / P bytes of
+ * library workspace, with blocks of P = 4096 particles from 2^18 up
+ * (2.1 GB at n = 2^20) and P = 2048 or 1024 below.  Outside that range the default
  * gathers every ordered pair per row with j-splits: below 2^13 in one launch
  * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
  * workspace and one int counter per 64 rows), otherwise with float64 row

@@ -297,6 +297,45 @@ __device__ __forceinline__ void adj_pair_once(const float4 &xk, const float4 &wk
     jm = __builtin_fmaf(r3, wkd, r * wk.w);
 }
 
+// adj_pair_once for ring tiles, with the j-side added straight into the
+// slot value ja: F = r^3 u with u = c - t d enters both sides as one FMA per
+// component (r^3 u to tk, -r^3 u to ja), and the j mass term likewise.
+__device__ __forceinline__ void adj_pair_fold(const float4 &xk, const float4 &wk, const float4 &q,
+                                              const float4 &wq, float eps2, float4 &tk, float4 &ja)
+{
+    const float dx = xk.x - q.x;
+    const float dy = xk.y - q.y;
+    const float dz = xk.z - q.z;
+    float s = __builtin_fmaf(dx, dx, eps2);
+    s = __builtin_fmaf(dy, dy, s);
+    s = __builtin_fmaf(dz, dz, s);
+    const float r = __builtin_amdgcn_rsqf(s);
+    const float r2 = r * r;
+    const float r3 = r * r2;
+    float wkd = wk.x * dx;
+    wkd = __builtin_fmaf(wk.y, dy, wkd);
+    wkd = __builtin_fmaf(wk.z, dz, wkd);
+    float wjd = wq.x * dx;
+    wjd = __builtin_fmaf(wq.y, dy, wjd);
+    wjd = __builtin_fmaf(wq.z, dz, wjd);
+    const float cd = __builtin_fmaf(q.w, wkd, -xk.w * wjd);
+    const float b = __builtin_fmaf(xk.w, wq.w, q.w * wk.w);
+    const float t = __builtin_fmaf(3.0f * r2, cd, b);
+    const float ux = __builtin_fmaf(-t, dx, __builtin_fmaf(q.w, wk.x, -xk.w * wq.x));
+    const float uy = __builtin_fmaf(-t, dy, __builtin_fmaf(q.w, wk.y, -xk.w * wq.y));
+    const float uz = __builtin_fmaf(-t, dz, __builtin_fmaf(q.w, wk.z, -xk.w * wq.z));
+    tk.x = __builtin_fmaf(r3, ux, tk.x);
+    tk.y = __builtin_fmaf(r3, uy, tk.y);
+    tk.z = __builtin_fmaf(r3, uz, tk.z);
+    tk.w = __builtin_fmaf(r, wq.w, tk.w);
+    tk.w = __builtin_fmaf(-r3, wjd, tk.w);
+    ja.x = __builtin_fmaf(-r3, ux, ja.x);
+    ja.y = __builtin_fmaf(-r3, uy, ja.y);
+    ja.z = __builtin_fmaf(-r3, uz, ja.z);
+    ja.w = __builtin_fmaf(r3, wkd, ja.w);
+    ja.w = __builtin_fmaf(r, wk.w, ja.w);
+}
+
 // The k-side alone, with the pair removed when `skip` holds (diagonal tiles).
 __device__ __forceinline__ void adj_row_term(const float4 &xk, const float4 &wk, const float4 &q,
                                              const float4 &wq, float eps2, bool skip, float4 &tk)
@@ -382,14 +421,50 @@ __device__ __forceinline__ void adj_tile_steps(const float4 (&xk)[K], const floa
     }
 }
 
+// Ring tiles: the tiles are staged twice (entries e and e + 64 hold
+// particle e) and the wave's j-side slots number 128, so lane l at step s
+// reads entry l + s and updates slot l + s with no index wrap (immediate
+// LDS offsets in the unrolled loop); particle e's j-side sum is slot e plus
+// slot e + 64, folded into slot e at the end.  Same scheme and ordering
+// argument as the forward pair-once kernel.
+template <int K>
+__device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const float4 (&wk)[K],
+                                               const float4 *tile_xm, const float4 *tile_wv,
+                                               float4 *slot, int lane, float eps2,
+                                               float4 (&tk)[K])
+{
+    const float4 *txm = tile_xm + lane;
+    const float4 *twv = tile_wv + lane;
+    float4 *sl = slot + lane;
+    float4 q = txm[0];
+    float4 wq = twv[0];
+#pragma unroll 4
+    for (int s = 0; s < 64; ++s) {
+        // keep this step's slot read after the previous step's write
+        __asm__ volatile("" ::: "memory");
+        float4 ja = sl[s];
+        const float4 qn = txm[s + 1];
+        const float4 wqn = twv[s + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) adj_pair_fold(xk[k], wk[k], q, wq, eps2, tk[k], ja);
+        sl[s] = ja;
+        q = qn;
+        wq = wqn;
+    }
+    __asm__ volatile("" ::: "memory");
+    const float4 lo = slot[lane];
+    const float4 hi = slot[lane + 64];
+    slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
+}
+
 template <int W, int K>
 __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 {
     constexpr int PB = W * 64 * K;
     constexpr int TPB = PB / 64;
-    __shared__ float4 tile_xm[64];
-    __shared__ float4 tile_wv[64];
-    __shared__ float4 jacc[W][64];
+    __shared__ float4 tile_xm[128];
+    __shared__ float4 tile_wv[128];
+    __shared__ float4 jacc[W][128];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -414,7 +489,6 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         }
         acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (int t = tid; t < W * 64; t += W * 64) (&jacc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     // this chunk's share of the block's tiles (diagonal first, then the ring
     // delta-major); all-padding tiles are skipped (uniform)
@@ -439,11 +513,15 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
     if (u < u1 && tid < 64) load_xw(A, jbase + tid, nxm, nwv);
 
     while (u < u1) {
-        __syncthreads();
+        __syncthreads();  // the previous tile and its slot sums are done
         if (tid < 64) {
             tile_xm[tid] = nxm;
             tile_wv[tid] = nwv;
+            tile_xm[tid + 64] = nxm;
+            tile_wv[tid + 64] = nwv;
         }
+        jacc[wv][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        jacc[wv][lane + 64] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         const int cur_u = u, cur_delta = delta, cur_base = jbase;
         for (++u; u < u1; ++u)
@@ -456,7 +534,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         float4 *slot = &jacc[wv][0];
         const bool diag = (cur_delta == 0);
         if (!diag)
-            adj_tile_steps<K, false>(xk, wk, kk, tile_xm, tile_wv, slot, lane, 0, 0, 0, eps2, tk);
+            adj_ring_steps<K>(xk, wk, tile_xm, tile_wv, slot, lane, eps2, tk);
         else
             adj_tile_steps<K, true>(xk, wk, kk, tile_xm, tile_wv, slot, lane, wv * K, cur_u,
                                     cur_base, eps2, tk);
@@ -472,7 +550,6 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         if (!diag) {
             if (tid < 64) {
                 float4 sum = jacc[0][tid];
-                jacc[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int w2 = 1; w2 < W; ++w2) {
                     const float4 v = jacc[w2][tid];
@@ -480,15 +557,14 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                     sum.y += v.y;
                     sum.z += v.z;
                     sum.w += v.w;
-                    jacc[w2][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 const int j = cur_base + tid;
                 if (j < n) A.partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
             }
         } else if (wv == cur_u / K) {
-            // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K)
+            // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K);
+            // the diagonal steps use slots 0..63 only
             float4 sum = jacc[0][lane];
-            jacc[0][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int w2 = 1; w2 < W; ++w2) {
                 const float4 v = jacc[w2][lane];
@@ -496,7 +572,6 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                 sum.y += v.y;
                 sum.z += v.z;
                 sum.w += v.w;
-                jacc[w2][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             const int kt = cur_u - wv * K;
 #pragma unroll
@@ -606,7 +681,7 @@ static int variant_index(const char *name)
 int backward_default_variant(int64_t n)
 {
     static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
-    static const int pair_once_small = variant_index("bwd_sym_w4_k2_o1");
+    static const int pair_once_small = variant_index("bwd_sym_w2_k2_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
     if (n > (1 << 20)) return gather;

@@ -121,8 +121,8 @@ template <int W, int K>
 __global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
 {
     constexpr int PB = W * 64 * K;
-    __shared__ float4 tile[64];
-    __shared__ float4 jacc[W][64];
+    __shared__ float4 tile[kTileLds];
+    __shared__ float4 jacc[W][kSlotLds];
     const int G = gridDim.x;
     const int g = blockIdx.x;
     for (int round = 0;; ++round) {
@@ -145,8 +145,8 @@ template <int W, int K>
 __global__ __launch_bounds__(W * 64) void batched_sym_dyn_kernel(BatSymArgs A, int *ctr)
 {
     constexpr int PB = W * 64 * K;
-    __shared__ float4 tile[64];
-    __shared__ float4 jacc[W][64];
+    __shared__ float4 tile[kTileLds];
+    __shared__ float4 jacc[W][kSlotLds];
     __shared__ int s_idx;
     for (;;) {
         __syncthreads();  // every thread has read the previous ticket

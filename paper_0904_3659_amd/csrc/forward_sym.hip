@@ -20,8 +20,8 @@ struct SymArgs {
 template <int W, int K>
 __global__ __launch_bounds__(W * 64) void forward_sym_kernel(SymArgs A)
 {
-    __shared__ float4 tile[64];
-    __shared__ float4 jacc[W][64];
+    __shared__ float4 tile[kTileLds];
+    __shared__ float4 jacc[W][kSlotLds];
     const int I = blockIdx.x / A.C;
     const int c = blockIdx.x - I * A.C;
     pair_once_block<W, K>(A.x, A.m, A.n, A.eps2, A.M, I, c, A.C, A.partial, tile, jacc);

@@ -21,16 +21,19 @@
 //   block's tile sequence (diagonal tiles, then ring tiles delta-major) is
 //   shared evenly among the C chunks.
 //
-// j-tiles of 64 particles are staged in LDS.  On a ring tile, lane l at
-// step s (0..63) meets particle (l + s) mod 64 of the tile: each step is a
-// permutation of the 64 particles over the 64 lanes, so every lane owns a
-// different per-wave LDS slot at every step.  A lane reads its slot at the
-// start of the step and writes it back at the end; the next step's owner of
-// that slot is another lane of the same wave, and one wave's LDS accesses
-// complete in issue order, so the sums are exact read-modify-writes in a
-// fixed order (no atomics; LDS atomics serialise and were 4x slower).  After
-// the 64 steps the W waves' slots are added in wave order and written as the
-// tile's partial.
+// j-tiles of 64 particles are staged in LDS twice over (entries e and
+// e + 64 hold particle e).  On a ring tile, lane l at step s (0..63) meets
+// particle (l + s) mod 64 of the tile, read from entry l + s: each step is a
+// permutation of the 64 particles over the 64 lanes, and the entry index
+// needs no wrap, so the unrolled loop addresses LDS with immediate offsets
+// from one base.  The j-side sums live in 128 per-wave LDS slots in the same
+// way: at step s lane l adds its K terms to slot l + s (read-modify-write),
+// so particle e collects in slots e and e + 64.  No two lanes touch the
+// same slot in a step; a slot's next writer is another lane of the same
+// wave, and one wave's LDS accesses complete in issue order, so the sums are
+// exact read-modify-writes in a fixed order (no atomics; LDS atomics
+// serialise and were 4x slower).  After the 64 steps the W waves' slot
+// pairs are added in wave order and written as the tile's partial.
 //
 // Partials (float4 per particle, [C + M/2][n]): slots 0..C-1 hold the i-side
 // sums of the C chunks; slot C+delta-1 holds what particle j in block J
@@ -49,6 +52,11 @@ namespace nbody {
 
 constexpr float kPadRow = 1e18f;
 constexpr float kPadCol = -1e18f;
+
+// LDS entries per staged j-tile (64 particles, stored twice) and per wave's
+// j-side slots.
+constexpr int kTileLds = 128;
+constexpr int kSlotLds = 128;
 
 __host__ __device__ __forceinline__ int ring_len(int I, int M)
 {
@@ -170,6 +178,67 @@ __device__ __forceinline__ void pair_once_term(float xi, float yi, float zi, flo
     }
 }
 
+// One pair of a ring tile: i-side added to (tx, ty, tz, tp), j-side added
+// to the slot value g (the chain of a step's K rows starts from the slot,
+// so no separate add folds it in).
+__device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, float mi, float4 q,
+                                               float eps2, float &tx, float &ty, float &tz,
+                                               float &tp, float4 &g)
+{
+    const float dx = xi - q.x;
+    const float dy = yi - q.y;
+    const float dz = zi - q.z;
+    float s2 = __builtin_fmaf(dx, dx, eps2);
+    s2 = __builtin_fmaf(dy, dy, s2);
+    s2 = __builtin_fmaf(dz, dz, s2);
+    const float r = __builtin_amdgcn_rsqf(s2);
+    const float r3 = r * (r * r);
+    const float f = q.w * r3;
+    tp = __builtin_fmaf(q.w, r, tp);
+    tx = __builtin_fmaf(f, dx, tx);
+    ty = __builtin_fmaf(f, dy, ty);
+    tz = __builtin_fmaf(f, dz, tz);
+    const float h = mi * r3;
+    g.x = __builtin_fmaf(-h, dx, g.x);
+    g.y = __builtin_fmaf(-h, dy, g.y);
+    g.z = __builtin_fmaf(-h, dz, g.z);
+    g.w = __builtin_fmaf(mi, r, g.w);
+}
+
+// The 64 steps of a ring tile for one wave: lane l meets the particle in
+// tile entry l + s at step s and adds its j-side terms to slot l + s.
+// `tile` has kTileLds entries (the tile twice), `slot` this wave's
+// kSlotLds slots.
+template <int K>
+__device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const float (&yi)[K],
+                                                const float (&zi)[K], const float (&mi)[K],
+                                                const float4 *tile, float4 *slot, int lane,
+                                                float eps2, float (&tx)[K], float (&ty)[K],
+                                                float (&tz)[K], float (&tp)[K])
+{
+    const float4 *tq = tile + lane;
+    float4 *sl = slot + lane;
+    float4 q = tq[0];
+#pragma unroll 8
+    for (int s = 0; s < 64; ++s) {
+        // Compiler-only barrier: this step's slot read stays after the
+        // previous step's slot write (another lane wrote the slot read here).
+        __asm__ volatile("" ::: "memory");
+        float4 g = sl[s];
+        const float4 qn = tq[s + 1];  // next step's particle (read-only tile)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k], g);
+        sl[s] = g;
+        q = qn;
+    }
+    // particle e collected in slots e and e + 64: fold them into slot e
+    __asm__ volatile("" ::: "memory");
+    const float4 lo = slot[lane];
+    const float4 hi = slot[lane + 64];
+    slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
+}
+
 // The 64 steps of one tile for one wave.  Lane l meets tile particle
 // (l + s) mod 64 at step s.  Ring tiles (DIAG false): every row tile meets
 // the tile pair-once.  Diagonal tile t (DIAG true): row tile a = a0 + k
@@ -238,7 +307,7 @@ template <int W, int K>
 __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                                                 const float *__restrict__ m, int n, float eps2,
                                                 int M, int I, int c, int C, float4 *partial,
-                                                float4 *tile, float4 (*jacc)[64])
+                                                float4 *tile, float4 (*jacc)[kSlotLds])
 {
     constexpr int PB = W * 64 * K;   // particles per block
     constexpr int TPB = PB / 64;     // 64-particle tiles per block
@@ -267,9 +336,6 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
 #pragma unroll
     for (int k = 0; k < K; ++k) ax[k] = ay[k] = az[k] = ap[k] = 0.0f;
 
-    __syncthreads();  // LDS buffers are free (callers may loop over blocks)
-    for (int t = tid; t < W * 64; t += W * 64) (&jacc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-
     // ---- this chunk's share of the block's tile sequence; tiles that hold
     // only padding are skipped (uniform).
     const int U = TPB + ring_len(I, M) * TPB;
@@ -290,8 +356,16 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     if (kPrefetch && u < u1 && tid < 64) next = load_particle(x, m, jbase + tid, n);
 
     while (u < u1) {
-        __syncthreads();  // previous tile and its j-slot sums are done
-        if (tid < 64) tile[tid] = kPrefetch ? next : load_particle(x, m, jbase + tid, n);
+        // previous tile and its j-slot sums are done (and the LDS buffers
+        // free on entry: callers may loop over blocks)
+        __syncthreads();
+        if (tid < 64) {
+            const float4 v = kPrefetch ? next : load_particle(x, m, jbase + tid, n);
+            tile[tid] = v;
+            tile[tid + 64] = v;
+        }
+        jacc[wv][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        jacc[wv][lane + 64] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         const int cur_u = u, cur_delta = delta, cur_base = jbase;
         for (++u; u < u1; ++u)
@@ -306,7 +380,7 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
         const bool diag = (cur_delta == 0);
         float4 *slot = &jacc[wv][0];
         if (!diag) {
-            tile_steps<K, false>(xi, yi, zi, mi, ii, tile, slot, lane, 0, 0, 0, eps2, tx, ty, tz, tp);
+            ring_tile_steps<K>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
         } else if (kOnceDiag) {
             tile_steps<K, true>(xi, yi, zi, mi, ii, tile, slot, lane, wv * K, t, cur_base, eps2, tx,
                                 ty, tz, tp);
@@ -332,8 +406,9 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
         __syncthreads();  // every wave's j-side slots are complete
         if (!diag) {
             if (tid < 64) {
+                // particle tid: every wave folded its slot tid + 64 into slot
+                // tid (ring_tile_steps); add the waves' slots in wave order
                 float4 sum = jacc[0][tid];
-                jacc[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int w2 = 1; w2 < W; ++w2) {
                     const float4 v = jacc[w2][tid];
@@ -341,15 +416,14 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                     sum.y += v.y;
                     sum.z += v.z;
                     sum.w += v.w;
-                    jacc[w2][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 const int j = cur_base + tid;
                 if (j < n) partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
             }
         } else if (kOnceDiag && wv == t / K) {
-            // this wave holds diagonal tile t's rows (lane-slot t % K)
+            // this wave holds diagonal tile t's rows (lane-slot t % K); the
+            // diagonal steps use slots 0..63 only
             float4 sum = jacc[0][lane];
-            jacc[0][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int w2 = 1; w2 < W; ++w2) {
                 const float4 v = jacc[w2][lane];
@@ -357,7 +431,6 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                 sum.y += v.y;
                 sum.z += v.z;
                 sum.w += v.w;
-                jacc[w2][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             const int kt = t - wv * K;
 #pragma unroll
