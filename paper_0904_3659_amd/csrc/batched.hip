@@ -131,8 +131,8 @@ __global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
         const int4 u = A.units[idx];
         const int ns = u.y;
         const int M = (ns + PB - 1) / PB;
-        pair_once_block<W, K>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
-                              A.partial + u.w, tile, jacc);
+        pair_once_block<W, K, true>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
+                                    A.partial + u.w, tile, jacc);
     }
 }
 
@@ -157,8 +157,8 @@ __global__ __launch_bounds__(W * 64) void batched_sym_dyn_kernel(BatSymArgs A, i
         const int4 u = A.units[idx];
         const int ns = u.y;
         const int M = (ns + PB - 1) / PB;
-        pair_once_block<W, K>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
-                              A.partial + u.w, tile, jacc);
+        pair_once_block<W, K, true>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
+                                    A.partial + u.w, tile, jacc);
     }
     if (threadIdx.x == 0) {
         // Every workgroup draws tickets until it fails once and only then

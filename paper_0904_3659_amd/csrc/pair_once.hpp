@@ -209,12 +209,15 @@ __device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, flo
 // tile entry l + s at step s and adds its j-side terms to slot l + s.
 // `tile` has kTileLds entries (the tile twice), `slot` this wave's
 // kSlotLds slots.
-template <int K>
+// PARTIAL: only the first kv row groups of the wave hold particles (the
+// last block of a system); the others are padding with mass 0, whose terms
+// are exactly zero on both sides, so skipping them changes no bit.
+template <int K, bool PARTIAL = false>
 __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const float (&yi)[K],
                                                 const float (&zi)[K], const float (&mi)[K],
                                                 const float4 *tile, float4 *slot, int lane,
                                                 float eps2, float (&tx)[K], float (&ty)[K],
-                                                float (&tz)[K], float (&tp)[K])
+                                                float (&tz)[K], float (&tp)[K], int kv = K)
 {
     const float4 *tq = tile + lane;
     float4 *sl = slot + lane;
@@ -228,7 +231,9 @@ __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const floa
         const float4 qn = tq[s + 1];  // next step's particle (read-only tile)
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k], g);
+            if (!PARTIAL || k < kv)
+                pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k],
+                               g);
         sl[s] = g;
         q = qn;
     }
@@ -303,7 +308,12 @@ __device__ __forceinline__ void tile_steps(const float (&xi)[K], const float (&y
 // index, and a > t skips it (that pair of tiles is met on diagonal tile a).
 // The j-side sums of a diagonal tile belong to rows of the same block; the
 // wave that holds tile t's rows adds them to its own accumulators.
-template <int W, int K>
+// SKIP_PAD: skip the ring-tile work of row groups that hold only padding
+// (bitwise neutral: their terms are exactly zero).  Worth it for ensembles
+// of small systems, where a last block is often part padding (5% of the
+// row-group work on the 4,096-system ensemble); single systems keep the
+// lighter loop.
+template <int W, int K, bool SKIP_PAD = false>
 __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                                                 const float *__restrict__ m, int n, float eps2,
                                                 int M, int I, int c, int C, float4 *partial,
@@ -335,6 +345,8 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     float ax[K], ay[K], az[K], ap[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ax[k] = ay[k] = az[k] = ap[k] = 0.0f;
+    // row groups of this wave that hold particles (K except in a last block)
+    const int kv = SKIP_PAD ? min(K, max(0, (n - (I * PB + wv * 64 * K) + 63) / 64)) : K;
 
     // ---- this chunk's share of the block's tile sequence; tiles that hold
     // only padding are skipped (uniform).
@@ -380,7 +392,11 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
         const bool diag = (cur_delta == 0);
         float4 *slot = &jacc[wv][0];
         if (!diag) {
-            ring_tile_steps<K>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+            if (!SKIP_PAD || kv == K)
+                ring_tile_steps<K>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+            else if (kv > 0)
+                ring_tile_steps<K, true>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp,
+                                         kv);
         } else if (kOnceDiag) {
             tile_steps<K, true>(xi, yi, zi, mi, ii, tile, slot, lane, wv * K, t, cur_base, eps2, tx,
                                 ty, tz, tp);
