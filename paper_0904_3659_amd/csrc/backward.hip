@@ -685,7 +685,7 @@ int backward_default_variant(int64_t n)
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
     if (n > (1 << 20)) return gather;
-    if (n >= (1 << 15)) return pair_once;
+    if (n >= (1 << 16)) return pair_once;
     if (n >= (1 << 13)) return pair_once_small;
     if (n >= (1 << 11)) return gather;
     return gather_small;

@@ -371,6 +371,8 @@ const Variant kVariants[] = {
     FWD_SYM_VARIANT(4, 4, 1),
     FWD_SYM_VARIANT(2, 8, 1),
     FWD_SYM_VARIANT(16, 4, 1),
+    FWD_SYM_VARIANT(2, 4, 1),
+    FWD_SYM_VARIANT(1, 4, 1),
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
@@ -411,13 +413,14 @@ int forward_default_variant(int64_t n)
     static const int pair_once_16 = variant_index("fwd_sym_w16_k4_o1");
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_o1");
+    static const int pair_once_1 = variant_index("fwd_sym_w1_k4_o1");
     if (n > (1 << 21)) return gather_big;
     // 16-wave blocks (4,096 particles) above 2^18 also halve the partial
     // workspace (8 n^2 / 4096 bytes: 2.1 GB at 2^20) against 8-wave ones
     if (n >= (1 << 18)) return pair_once_16;
     if (n >= (1 << 17)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
-    if (n >= (1 << 15)) return pair_once_16;
+    if (n >= 3 * (1 << 12)) return pair_once_1;
     if (n >= (1 << 13)) return gather_mid;
     // Small n is set by launch latency: one launch, no reduction kernel.
     return one_launch;
