@@ -1,0 +1,46 @@
+"""bench.py's host-side contract, checked on the CPU: one GPU only, the
+CPU-baseline record, and the traffic figure's source/variant key."""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_0904_3659_amd import inputs  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_cpu_baseline_record():
+    n = 512
+    w = inputs.Workload("plummer_n512_test", inputs.plummer_positions(n, (90, 0)),
+                        inputs.equal_masses(n), 1e-4)
+    rec = bench.cpu_baseline(w, budget_s=0.5)
+    assert rec["kind"] == "oracle" and rec["unit"] == "pair-interactions/s"
+    assert rec["value"] > 0 and rec["single_thread_value"] > 0 and rec["cores"] >= 1
+    assert "seeded rows" in rec["sample"]
+
+
+def test_traffic_figure_is_keyed_to_variant_and_sources():
+    # another variant never picks up the recorded figure
+    assert bench.read_traffic("fwd_b256_k1_u8") is None
+    # the recorded file parses and names the kernel source hash it was taken on
+    kv = {}
+    for line in open(bench.TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    assert len(kv["kernel_source_sha"]) == 16 and kv["variant"].startswith("fwd_sym")
+    assert float(kv["hbm_bytes_per_launch"]) > float(kv["algorithmic_bytes_per_launch"]) > 0
+    if kv["kernel_source_sha"] == bench.forward_source_sha():
+        assert bench.read_traffic(kv["variant"]) == float(kv["hbm_bytes_per_launch"])
