@@ -154,6 +154,37 @@ def graph_plain_ms(plain, ab, pb, torch):
     return ms if ok else None
 
 
+SWEEP_SIZES = (1024, 2048, 4096, 7500, 10000, 16384, 18000, 32768, 65536, 100000, 262144,
+               1048576)
+SWEEP_PROGRAMS = (("gpu-no-unrolling", "fwd_b256_k1_u1"), ("simple-unrolling", "fwd_b256_k4_u1"),
+                  ("double-unrolling", "fwd_b256_k4_u4"), ("default", None))
+
+
+def size_sweep(nb, torch, dev, inputs, metrics):
+    """pairs/s of the paper's three GPU programs (Sec. IV, Figs. no-u, sim-u,
+    double-u as (K, U) = (1, 1), (4, 1), (4, 4) gathers) and of the default
+    variant against N: Plummer spheres, masses 1/N, eps2 = 1e-4."""
+    names = nb.variant_names(nb.FORWARD)
+    table = {}
+    for n in SWEEP_SIZES:
+        x = torch.from_numpy(inputs.plummer_positions(n, (8, n))).to(dev)
+        m = torch.from_numpy(inputs.equal_masses(n)).to(dev)
+        reps = max(3, min(50, int(4e11 / (n * n))))
+        row = {}
+        for label, vname in SWEEP_PROGRAMS:
+            nb.set_variant(nb.FORWARD, names.index(vname) if vname else -1)
+            f = lambda: nb.forces(x, m, 1e-4)
+            f()
+            wall, _, _ = timed_calls(f, reps, torch, nb)
+            row[label] = {"variant": vname or names[nb.selected_variant(nb.FORWARD, n)],
+                          "ms": wall * 1e3 / reps,
+                          "pairs_per_s": metrics.pairs(n) / (wall / reps)}
+        nb.set_variant(nb.FORWARD, -1)
+        table[str(n)] = row
+        log(f"size sweep n={n}: " + ", ".join(f"{k} {v['pairs_per_s']:.3e}" for k, v in row.items()))
+    return table
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +192,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--only-forward", action="store_true", help="skip adjoint and batched legs")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the legs, time the paper's three unrolling programs and "
+                         "the default variant over a range of N (pairs/s vs N)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES (the reference "
                          "kernel that scales the HBM byte counters)")
@@ -179,6 +213,10 @@ def main() -> int:
         return 2
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.size_sweep:
+        print(json.dumps({"size_sweep": size_sweep(nb, torch, dev, inputs, metrics),
+                          "unit": "pair-interactions/s", "data": "synthetic"}), flush=True)
+        return 0
 
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)

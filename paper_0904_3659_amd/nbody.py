@@ -10,6 +10,7 @@ raises at first use.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -95,6 +96,13 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _on(device: torch.device):
+    """Make ``device`` current for the call (a no-op when it already is)."""
+    if device.index is None or device.index == torch.cuda.current_device():
+        return contextlib.nullcontext()
+    return torch.cuda.device(device)
+
+
 def _stream(device: torch.device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -146,7 +154,7 @@ def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential
         _want(a, "a", (n, 3), dev)
         if p is not None:
             _want(p, "p", (n,), dev)
-    with torch.cuda.device(dev):
+    with _on(dev):
         if f64_sum:
             _check(lib().nbody_forces_ex(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p),
                                          F64_SUM, _stream(dev)))
@@ -174,7 +182,7 @@ def forces_backward(x, m, eps2, grad_a=None, grad_p=None, *, need_grad_m: bool =
         _want(gx, "grad_x", (n, 3), dev)
         if gm is not None:
             _want(gm, "grad_m", (n,), dev)
-    with torch.cuda.device(dev):
+    with _on(dev):
         _check(lib().nbody_forces_backward(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(grad_a),
                                            _ptr(grad_p), _ptr(gx), _ptr(gm), _stream(dev)))
     return gx, gm
@@ -210,7 +218,7 @@ def forces_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float, *, ou
         a, p = out
         _want(a, "a", (n, 3), dev)
         _want(p, "p", (n,), dev)
-    with torch.cuda.device(dev):
+    with _on(dev):
         _check(lib().nbody_forces_batched(o.ctypes.data_as(ctypes.POINTER(_i64)), o.size - 1,
                                           _ptr(x), _ptr(m), _eps2(eps2), _ptr(a), _ptr(p),
                                           _stream(dev)))
@@ -221,7 +229,7 @@ def axpy_(y: torch.Tensor, xv: torch.Tensor, alpha: float) -> torch.Tensor:
     """In place y += alpha * xv on the device (leap-frog kick and drift)."""
     _want(y, "y", tuple(y.shape))
     _want(xv, "x", tuple(y.shape), y.device)
-    with torch.cuda.device(y.device):
+    with _on(y.device):
         _check(lib().nbody_axpy(_ptr(y), _ptr(xv), y.numel(), float(alpha), _stream(y.device)))
     return y
 
@@ -232,7 +240,7 @@ def kick_drift_(x: torch.Tensor, v: torch.Tensor, a: torch.Tensor, kick: float, 
     _want(x, "x", (n, 3))
     _want(v, "v", (n, 3), x.device)
     _want(a, "a", (n, 3), x.device)
-    with torch.cuda.device(x.device):
+    with _on(x.device):
         _check(lib().nbody_kick_drift(_ptr(x), _ptr(v), _ptr(a), n, float(kick), float(dt),
                                       _stream(x.device)))
     return x, v
@@ -286,7 +294,7 @@ def autotune(kind: int, sizes, device=None) -> None:
     """Time every variant of ``kind`` at each size and keep the fastest."""
     s = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-    with torch.cuda.device(dev):
+    with _on(dev):
         _check(lib().nbody_autotune(kind, s.ctypes.data_as(ctypes.POINTER(_i64)), s.size, _stream(dev)))
 
 
