@@ -200,8 +200,8 @@ def main() -> int:
                          "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the path runs on a single MI355X "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the path runs on a single MI355X and "
+              "sharding over several GPUs is not built; run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch

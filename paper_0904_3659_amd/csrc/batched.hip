@@ -55,8 +55,8 @@ __global__ __launch_bounds__(BLOCK) void batched_kernel(BatArgs P)
     const int g = blockIdx.x;
     const float eps2 = P.eps2;
 
-    for (int round = 0;; ++round) {
-        const int idx = (round & 1) ? round * G + (G - 1 - g) : round * G + g;
+    for (int pass = 0;; ++pass) {
+        const int idx = (pass & 1) ? pass * G + (G - 1 - g) : pass * G + g;
         if (idx >= P.num_units) break;
         const int4 w = P.units[idx];
         const int i0 = w.x, iend = w.y, jbeg = w.z, jend = w.w;
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
     __shared__ float4 jacc[W][kSlotLds];
     const int G = gridDim.x;
     const int g = blockIdx.x;
-    for (int round = 0;; ++round) {
-        const int idx = (round & 1) ? round * G + (G - 1 - g) : round * G + g;
+    for (int pass = 0;; ++pass) {
+        const int idx = (pass & 1) ? pass * G + (G - 1 - g) : pass * G + g;
         if (idx >= A.num_units) break;
         const int4 u = A.units[idx];
         const int ns = u.y;

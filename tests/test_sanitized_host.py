@@ -1,12 +1,12 @@
 """Host-side sanitizer runs (CPU only).
 
 The FP64 reference is rebuilt with AddressSanitizer and UndefinedBehavior
-Sanitizer into a small C driver that exercises every entry point (optional
-NULL arguments, row subsets, empty systems, the integrator), and the driver
-must finish cleanly.  The host half of the HIP library (argument checks,
-variant tables, tuning-cache parsing) is rebuilt the same way, sanitizing
-host code only, and a driver walks its argument-check paths, none of which
-touches a GPU.
+Sanitizer into a small C test program that exercises every entry point
+(optional NULL arguments, row subsets, empty systems, the integrator), and
+the program must finish cleanly.  The host half of the HIP library
+(argument checks, variant tables, tuning-cache parsing) is rebuilt the same
+way, sanitizing host code only, and a test program walks its argument-check
+paths, none of which touches a GPU.
 """
 
 import os
@@ -20,7 +20,7 @@ from oracle import build as OB
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN = ["-fsanitize=" + "address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all"]
 
-ORACLE_DRIVER = r"""
+ORACLE_PROGRAM = r"""
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -67,7 +67,7 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     drv = tmp_path / "drv.c"
-    drv.write_text(ORACLE_DRIVER)
+    drv.write_text(ORACLE_PROGRAM)
     exe = tmp_path / "drv"
     flags = [f for f in OB.CFLAGS if f not in ("-shared", "-fPIC")]
     subprocess.run(["gcc", *flags, *SAN, str(drv), OB.SOURCE, "-o", str(exe), "-lm"], check=True)
@@ -78,7 +78,7 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     assert out.stdout.strip() == "ok"
 
 
-LIB_DRIVER = r"""
+LIB_PROGRAM = r"""
 #include <stdint.h>
 #include <stdio.h>
 #include <math.h>
@@ -129,9 +129,9 @@ def test_library_host_code_under_sanitizers(tmp_path):
     subprocess.run([hipcc, *flags, "--offload-arch=gfx950", *host_san, *LB.sources(), "-o", str(lib)],
                    check=True, capture_output=True)
     drv = tmp_path / "drv.c"
-    drv.write_text(LIB_DRIVER)
+    drv.write_text(LIB_PROGRAM)
     exe = tmp_path / "drv"
-    # the driver links the same (clang) sanitizer runtime as the library
+    # the test program links the same (clang) sanitizer runtime as the library
     clang = os.path.join(os.path.dirname(os.path.realpath(hipcc)), "..", "lib", "llvm", "bin", "clang")
     if not os.path.exists(clang):
         clang = shutil.which("clang") or pytest.skip("clang not available")
