@@ -244,6 +244,83 @@ __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const floa
     slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
 }
 
+// One step s of a diagonal tile: rows k < R meet entry l + s pair-once.
+template <int K, int R>
+__device__ __forceinline__ void diag_step(const float (&xi)[K], const float (&yi)[K],
+                                          const float (&zi)[K], const float (&mi)[K],
+                                          const float4 *tq, float4 *sl, int s, float eps2,
+                                          float (&tx)[K], float (&ty)[K], float (&tz)[K],
+                                          float (&tp)[K])
+{
+    if constexpr (R > 0) {
+        // keep this step's slot read after the previous step's slot write
+        __asm__ volatile("" ::: "memory");
+        const float4 q = tq[s];
+        float4 g = sl[s];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k], g);
+        sl[s] = g;
+    }
+}
+
+// Diagonal tile whose rows are this wave's row group KT (rows k < KT belong
+// to earlier tiles of the block and meet it pair-once; rows k > KT to later
+// ones, which meet it from their side).  Row group KT meets its own tile
+// pair-once too: lane l and particle l + s (mod 64) form each unordered
+// pair once for s = 1..31, and for s = 32 the pair {l, l + 32} is met by
+// both lanes, so each takes its i-side only; s = 0 (the particle itself)
+// and s = 33..63 (met as 64 - s by the partner) are skipped.  The j-side
+// sums fill this wave's slots like a ring tile's and are folded to slot e.
+template <int K, int KT>
+__device__ __forceinline__ void diag_self_steps(const float (&xi)[K], const float (&yi)[K],
+                                                const float (&zi)[K], const float (&mi)[K],
+                                                const float4 *tile, float4 *slot, int lane,
+                                                float eps2, float (&tx)[K], float (&ty)[K],
+                                                float (&tz)[K], float (&tp)[K])
+{
+    const float4 *tq = tile + lane;
+    float4 *sl = slot + lane;
+    // The loops run two steps per trip and are kept rolled: fully unrolled,
+    // the K instances of this function made a kernel larger than the
+    // instruction cache and slowed its ring loop.
+    diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 0, eps2, tx, ty, tz, tp);
+#pragma nounroll
+    for (int s = 1; s < 31; s += 2) {
+        diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
+        diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
+    }
+    diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, 31, eps2, tx, ty, tz, tp);
+    diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 32, eps2, tx, ty, tz, tp);
+    pair_term(xi[KT], yi[KT], zi[KT], tq[32], eps2, tx[KT], ty[KT], tz[KT], tp[KT]);
+    if (KT > 0) {
+#pragma nounroll
+        for (int s = 33; s < 63; s += 2) {
+            diag_step<K, KT>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
+            diag_step<K, KT>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
+        }
+        diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 63, eps2, tx, ty, tz, tp);
+    }
+    __asm__ volatile("" ::: "memory");
+    const float4 lo = slot[lane];
+    const float4 hi = slot[lane + 64];
+    slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
+}
+
+template <int K, int KT = 0>
+__device__ __forceinline__ void diag_tile_dispatch(int kt, const float (&xi)[K],
+                                                   const float (&yi)[K], const float (&zi)[K],
+                                                   const float (&mi)[K], const float4 *tile,
+                                                   float4 *slot, int lane, float eps2,
+                                                   float (&tx)[K], float (&ty)[K], float (&tz)[K],
+                                                   float (&tp)[K])
+{
+    if (kt == KT)
+        diag_self_steps<K, KT>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+    else if constexpr (KT + 1 < K)
+        diag_tile_dispatch<K, KT + 1>(kt, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+}
+
 // The 64 steps of one tile for one wave.  Lane l meets tile particle
 // (l + s) mod 64 at step s.  Ring tiles (DIAG false): every row tile meets
 // the tile pair-once.  Diagonal tile t (DIAG true): row tile a = a0 + k
@@ -305,7 +382,8 @@ __device__ __forceinline__ void tile_steps(const float (&xi)[K], const float (&y
 // masked ordered pairs): the rows of lane-slot k of wave wv form
 // the block's tile a = wv*K + k.  On diagonal tile t, row tile a < t meets
 // it pair-once, a == t meets it as ordered pairs with j == i removed by
-// index, and a > t skips it (that pair of tiles is met on diagonal tile a).
+// index (one-wave blocks: pair-once within the tile, diag_self_steps), and
+// a > t skips it (that pair of tiles is met on diagonal tile a).
 // The j-side sums of a diagonal tile belong to rows of the same block; the
 // wave that holds tile t's rows adds them to its own accumulators.
 // SKIP_PAD: skip the ring-tile work of row groups that hold only padding
@@ -361,6 +439,13 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     // 16-wave blocks meet them as masked ordered pairs (at 2^17 particles
     // and up the diagonal is under 1/32 of the pairs).
     constexpr bool kOnceDiag = (W <= 8);
+    // One-wave blocks (ensembles of small systems, mid-size single systems,
+    // where diagonal tiles are a fifth of the work) also meet each diagonal
+    // tile's own 64 particles pair-once (diag_self_steps).  Wider blocks
+    // keep the masked ordered self tile: there the diagonal is rare, and
+    // the larger code changed the schedule of their ring loop (6-8% slower
+    // at 2^20 bodies).
+    constexpr bool kSelfDiag = (W == 1);
     int u = u0, delta = 0, jbase = 0;
     for (; u < u1; ++u)
         if ((jbase = tile_base<PB>(u, I, M, delta)) < n) break;
@@ -397,6 +482,10 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
             else if (kv > 0)
                 ring_tile_steps<K, true>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp,
                                          kv);
+        } else if constexpr (kSelfDiag) {
+            // one wave: its row group k is the block's tile k, so diagonal
+            // tile t meets row groups k < t pair-once and row group t itself
+            diag_tile_dispatch<K>(t, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
         } else if (kOnceDiag) {
             tile_steps<K, true>(xi, yi, zi, mi, ii, tile, slot, lane, wv * K, t, cur_base, eps2, tx,
                                 ty, tz, tp);
@@ -438,7 +527,7 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
             }
         } else if (kOnceDiag && wv == t / K) {
             // this wave holds diagonal tile t's rows (lane-slot t % K); the
-            // diagonal steps use slots 0..63 only
+            // diagonal steps leave their sums in slots 0..63
             float4 sum = jacc[0][lane];
 #pragma unroll
             for (int w2 = 1; w2 < W; ++w2) {
