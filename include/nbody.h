@@ -82,7 +82,8 @@ const char *nbody_last_error(void);
  * potential m_i/eps appears.  One softening eps2 = eps^2 serves every pair.
  *
  * x: [n][3] in, m: [n] in, a: [n][3] out, p: [n] out (p may be NULL to skip
- * the potential store; the sum is still formed).
+ * the potential; the pair-once kernels then do not form its terms, and a is
+ * bitwise the same as with p).
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.

@@ -17,14 +17,14 @@ struct SymArgs {
     float4 *partial;  // [C + M/2][n]
 };
 
-template <int W, int K>
+template <int W, int K, bool POT>
 __global__ __launch_bounds__(W * 64) void forward_sym_kernel(SymArgs A)
 {
     __shared__ float4 tile[kTileLds];
     __shared__ float4 jacc[W][kSlotLds];
     const int I = blockIdx.x / A.C;
     const int c = blockIdx.x - I * A.C;
-    pair_once_block<W, K>(A.x, A.m, A.n, A.eps2, A.M, I, c, A.C, A.partial, tile, jacc);
+    pair_once_block<W, K, false, POT>(A.x, A.m, A.n, A.eps2, A.M, I, c, A.C, A.partial, tile, jacc);
 }
 
 // OCC divides the chunk count: 1 fills every resident workgroup slot once;
@@ -37,8 +37,10 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     constexpr int PB = W * 64 * K;
     const int M = (n + PB - 1) / PB;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, forward_sym_kernel<W, K>,
-                                                                W * 64, 0);
+    // sized by the kernel that forms the potential, also when p is not
+    // stored: the same chunking keeps a bitwise the same either way
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, forward_sym_kernel<W, K, true>, W * 64, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     const int resident = per_cu * dev.num_cu;
@@ -54,7 +56,11 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     SymArgs A{x, m, n, eps2, M, C, static_cast<float4 *>(ws)};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
     prof_mark(stream, 0);
-    hipLaunchKernelGGL((forward_sym_kernel<W, K>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    if (p)
+        hipLaunchKernelGGL((forward_sym_kernel<W, K, true>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    else
+        hipLaunchKernelGGL((forward_sym_kernel<W, K, false>), dim3(M * C), dim3(W * 64), 0, stream,
+                           A);
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;

@@ -180,7 +180,10 @@ __device__ __forceinline__ void pair_once_term(float xi, float yi, float zi, flo
 
 // One pair of a ring tile: i-side added to (tx, ty, tz, tp), j-side added
 // to the slot value g (the chain of a step's K rows starts from the slot,
-// so no separate add folds it in).
+// so no separate add folds it in).  POT false: the caller stores no
+// potential, and its two terms (2 of the pair's 19 instructions) are not
+// formed.
+template <bool POT = true>
 __device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, float mi, float4 q,
                                                float eps2, float &tx, float &ty, float &tz,
                                                float &tp, float4 &g)
@@ -194,7 +197,7 @@ __device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, flo
     const float r = __builtin_amdgcn_rsqf(s2);
     const float r3 = r * (r * r);
     const float f = q.w * r3;
-    tp = __builtin_fmaf(q.w, r, tp);
+    if (POT) tp = __builtin_fmaf(q.w, r, tp);
     tx = __builtin_fmaf(f, dx, tx);
     ty = __builtin_fmaf(f, dy, ty);
     tz = __builtin_fmaf(f, dz, tz);
@@ -202,7 +205,7 @@ __device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, flo
     g.x = __builtin_fmaf(-h, dx, g.x);
     g.y = __builtin_fmaf(-h, dy, g.y);
     g.z = __builtin_fmaf(-h, dz, g.z);
-    g.w = __builtin_fmaf(mi, r, g.w);
+    if (POT) g.w = __builtin_fmaf(mi, r, g.w);
 }
 
 // The 64 steps of a ring tile for one wave: lane l meets the particle in
@@ -212,7 +215,7 @@ __device__ __forceinline__ void pair_once_fold(float xi, float yi, float zi, flo
 // PARTIAL: only the first kv row groups of the wave hold particles (the
 // last block of a system); the others are padding with mass 0, whose terms
 // are exactly zero on both sides, so skipping them changes no bit.
-template <int K, bool PARTIAL = false>
+template <int K, bool PARTIAL = false, bool POT = true>
 __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const float (&yi)[K],
                                                 const float (&zi)[K], const float (&mi)[K],
                                                 const float4 *tile, float4 *slot, int lane,
@@ -232,7 +235,7 @@ __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const floa
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (!PARTIAL || k < kv)
-                pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k],
+                pair_once_fold<POT>(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k],
                                g);
         sl[s] = g;
         q = qn;
@@ -245,7 +248,7 @@ __device__ __forceinline__ void ring_tile_steps(const float (&xi)[K], const floa
 }
 
 // One step s of a diagonal tile: rows k < R meet entry l + s pair-once.
-template <int K, int R>
+template <int K, int R, bool POT = true>
 __device__ __forceinline__ void diag_step(const float (&xi)[K], const float (&yi)[K],
                                           const float (&zi)[K], const float (&mi)[K],
                                           const float4 *tq, float4 *sl, int s, float eps2,
@@ -259,7 +262,7 @@ __device__ __forceinline__ void diag_step(const float (&xi)[K], const float (&yi
         float4 g = sl[s];
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            pair_once_fold(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k], g);
+            pair_once_fold<POT>(xi[k], yi[k], zi[k], mi[k], q, eps2, tx[k], ty[k], tz[k], tp[k], g);
         sl[s] = g;
     }
 }
@@ -272,7 +275,7 @@ __device__ __forceinline__ void diag_step(const float (&xi)[K], const float (&yi
 // both lanes, so each takes its i-side only; s = 0 (the particle itself)
 // and s = 33..63 (met as 64 - s by the partner) are skipped.  The j-side
 // sums fill this wave's slots like a ring tile's and are folded to slot e.
-template <int K, int KT>
+template <int K, int KT, bool POT = true>
 __device__ __forceinline__ void diag_self_steps(const float (&xi)[K], const float (&yi)[K],
                                                 const float (&zi)[K], const float (&mi)[K],
                                                 const float4 *tile, float4 *slot, int lane,
@@ -284,22 +287,22 @@ __device__ __forceinline__ void diag_self_steps(const float (&xi)[K], const floa
     // The loops run two steps per trip and are kept rolled: fully unrolled,
     // the K instances of this function made a kernel larger than the
     // instruction cache and slowed its ring loop.
-    diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 0, eps2, tx, ty, tz, tp);
+    diag_step<K, KT, POT>(xi, yi, zi, mi, tq, sl, 0, eps2, tx, ty, tz, tp);
 #pragma nounroll
     for (int s = 1; s < 31; s += 2) {
-        diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
-        diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
+        diag_step<K, KT + 1, POT>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
+        diag_step<K, KT + 1, POT>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
     }
-    diag_step<K, KT + 1>(xi, yi, zi, mi, tq, sl, 31, eps2, tx, ty, tz, tp);
-    diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 32, eps2, tx, ty, tz, tp);
+    diag_step<K, KT + 1, POT>(xi, yi, zi, mi, tq, sl, 31, eps2, tx, ty, tz, tp);
+    diag_step<K, KT, POT>(xi, yi, zi, mi, tq, sl, 32, eps2, tx, ty, tz, tp);
     pair_term(xi[KT], yi[KT], zi[KT], tq[32], eps2, tx[KT], ty[KT], tz[KT], tp[KT]);
     if (KT > 0) {
 #pragma nounroll
         for (int s = 33; s < 63; s += 2) {
-            diag_step<K, KT>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
-            diag_step<K, KT>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
+            diag_step<K, KT, POT>(xi, yi, zi, mi, tq, sl, s, eps2, tx, ty, tz, tp);
+            diag_step<K, KT, POT>(xi, yi, zi, mi, tq, sl, s + 1, eps2, tx, ty, tz, tp);
         }
-        diag_step<K, KT>(xi, yi, zi, mi, tq, sl, 63, eps2, tx, ty, tz, tp);
+        diag_step<K, KT, POT>(xi, yi, zi, mi, tq, sl, 63, eps2, tx, ty, tz, tp);
     }
     __asm__ volatile("" ::: "memory");
     const float4 lo = slot[lane];
@@ -307,7 +310,7 @@ __device__ __forceinline__ void diag_self_steps(const float (&xi)[K], const floa
     slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
 }
 
-template <int K, int KT = 0>
+template <int K, int KT = 0, bool POT = true>
 __device__ __forceinline__ void diag_tile_dispatch(int kt, const float (&xi)[K],
                                                    const float (&yi)[K], const float (&zi)[K],
                                                    const float (&mi)[K], const float4 *tile,
@@ -316,9 +319,9 @@ __device__ __forceinline__ void diag_tile_dispatch(int kt, const float (&xi)[K],
                                                    float (&tp)[K])
 {
     if (kt == KT)
-        diag_self_steps<K, KT>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+        diag_self_steps<K, KT, POT>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
     else if constexpr (KT + 1 < K)
-        diag_tile_dispatch<K, KT + 1>(kt, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+        diag_tile_dispatch<K, KT + 1, POT>(kt, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
 }
 
 // The 64 steps of one tile for one wave.  Lane l meets tile particle
@@ -386,12 +389,14 @@ __device__ __forceinline__ void tile_steps(const float (&xi)[K], const float (&y
 // a > t skips it (that pair of tiles is met on diagonal tile a).
 // The j-side sums of a diagonal tile belong to rows of the same block; the
 // wave that holds tile t's rows adds them to its own accumulators.
+// POT false: no potential is stored, and the ring and one-wave diagonal
+// tiles do not form its terms (the partials' w component is then partial).
 // SKIP_PAD: skip the ring-tile work of row groups that hold only padding
 // (bitwise neutral: their terms are exactly zero).  Worth it for ensembles
 // of small systems, where a last block is often part padding (5% of the
 // row-group work on the 4,096-system ensemble); single systems keep the
 // lighter loop.
-template <int W, int K, bool SKIP_PAD = false>
+template <int W, int K, bool SKIP_PAD = false, bool POT = true>
 __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                                                 const float *__restrict__ m, int n, float eps2,
                                                 int M, int I, int c, int C, float4 *partial,
@@ -478,14 +483,14 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
         float4 *slot = &jacc[wv][0];
         if (!diag) {
             if (!SKIP_PAD || kv == K)
-                ring_tile_steps<K>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+                ring_tile_steps<K, false, POT>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
             else if (kv > 0)
-                ring_tile_steps<K, true>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp,
+                ring_tile_steps<K, true, POT>(xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp,
                                          kv);
         } else if constexpr (kSelfDiag) {
             // one wave: its row group k is the block's tile k, so diagonal
             // tile t meets row groups k < t pair-once and row group t itself
-            diag_tile_dispatch<K>(t, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
+            diag_tile_dispatch<K, 0, POT>(t, xi, yi, zi, mi, tile, slot, lane, eps2, tx, ty, tz, tp);
         } else if (kOnceDiag) {
             tile_steps<K, true>(xi, yi, zi, mi, ii, tile, slot, lane, wv * K, t, cur_base, eps2, tx,
                                 ty, tz, tp);

@@ -300,3 +300,16 @@ def test_f64_sum_at_four_million(nb):
     print(f"[parity] {w.name} float32 sums {e32}  float64 sums {e64}", flush=True)
     assert max(e64) <= 1e-6
     assert max(e64) * 10 <= max(e32)
+
+
+@pytest.mark.parametrize("n", [20000, 70000])
+def test_no_potential_kernel_same_acceleration(nb, n):
+    # without p the pair-once kernels skip the potential terms; the
+    # acceleration must not change by a bit
+    dev = need_gpu()
+    x = to_dev(inputs.plummer_positions(n, (65, n)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (65, n, 1)), dev)
+    assert nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, n)].startswith("fwd_sym")
+    a_p, p = nb.forces(x, m, 1e-4)
+    a_n, none = nb.forces(x, m, 1e-4, potential=False)
+    assert none is None and torch.equal(a_p, a_n)
