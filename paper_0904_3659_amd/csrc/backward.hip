@@ -300,6 +300,7 @@ __device__ __forceinline__ void adj_pair_once(const float4 &xk, const float4 &wk
 // adj_pair_once for ring tiles, with the j-side added straight into the
 // slot value ja: F = r^3 u with u = c - t d enters both sides as one FMA per
 // component (r^3 u to tk, -r^3 u to ja), and the j mass term likewise.
+template <bool HAS_V = true>
 __device__ __forceinline__ void adj_pair_fold(const float4 &xk, const float4 &wk, const float4 &q,
                                               const float4 &wq, float eps2, float4 &tk, float4 &ja)
 {
@@ -319,21 +320,23 @@ __device__ __forceinline__ void adj_pair_fold(const float4 &xk, const float4 &wk
     wjd = __builtin_fmaf(wq.y, dy, wjd);
     wjd = __builtin_fmaf(wq.z, dz, wjd);
     const float cd = __builtin_fmaf(q.w, wkd, -xk.w * wjd);
-    const float b = __builtin_fmaf(xk.w, wq.w, q.w * wk.w);
-    const float t = __builtin_fmaf(3.0f * r2, cd, b);
+    // without potential weights (v = 0) b vanishes and t = 3 r^2 (c . d)
+    // exactly as the fused form with a zero addend
+    const float t = HAS_V ? __builtin_fmaf(3.0f * r2, cd, __builtin_fmaf(xk.w, wq.w, q.w * wk.w))
+                          : (3.0f * r2) * cd;
     const float ux = __builtin_fmaf(-t, dx, __builtin_fmaf(q.w, wk.x, -xk.w * wq.x));
     const float uy = __builtin_fmaf(-t, dy, __builtin_fmaf(q.w, wk.y, -xk.w * wq.y));
     const float uz = __builtin_fmaf(-t, dz, __builtin_fmaf(q.w, wk.z, -xk.w * wq.z));
     tk.x = __builtin_fmaf(r3, ux, tk.x);
     tk.y = __builtin_fmaf(r3, uy, tk.y);
     tk.z = __builtin_fmaf(r3, uz, tk.z);
-    tk.w = __builtin_fmaf(r, wq.w, tk.w);
+    if (HAS_V) tk.w = __builtin_fmaf(r, wq.w, tk.w);
     tk.w = __builtin_fmaf(-r3, wjd, tk.w);
     ja.x = __builtin_fmaf(-r3, ux, ja.x);
     ja.y = __builtin_fmaf(-r3, uy, ja.y);
     ja.z = __builtin_fmaf(-r3, uz, ja.z);
     ja.w = __builtin_fmaf(r3, wkd, ja.w);
-    ja.w = __builtin_fmaf(r, wk.w, ja.w);
+    if (HAS_V) ja.w = __builtin_fmaf(r, wk.w, ja.w);
 }
 
 // The k-side alone, with the pair removed when `skip` holds (diagonal tiles).
@@ -427,7 +430,7 @@ __device__ __forceinline__ void adj_tile_steps(const float4 (&xk)[K], const floa
 // LDS offsets in the unrolled loop); particle e's j-side sum is slot e plus
 // slot e + 64, folded into slot e at the end.  Same scheme and ordering
 // argument as the forward pair-once kernel.
-template <int K>
+template <int K, bool HAS_V = true>
 __device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const float4 (&wk)[K],
                                                const float4 *tile_xm, const float4 *tile_wv,
                                                float4 *slot, int lane, float eps2,
@@ -446,7 +449,7 @@ __device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const floa
         const float4 qn = txm[s + 1];
         const float4 wqn = twv[s + 1];
 #pragma unroll
-        for (int k = 0; k < K; ++k) adj_pair_fold(xk[k], wk[k], q, wq, eps2, tk[k], ja);
+        for (int k = 0; k < K; ++k) adj_pair_fold<HAS_V>(xk[k], wk[k], q, wq, eps2, tk[k], ja);
         sl[s] = ja;
         q = qn;
         wq = wqn;
@@ -457,7 +460,9 @@ __device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const floa
     slot[lane] = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
 }
 
-template <int W, int K>
+// HAS_V false: no potential weights (grad_p NULL); their terms are not
+// formed on ring tiles (bitwise the same result as v = 0).
+template <int W, int K, bool HAS_V>
 __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 {
     constexpr int PB = W * 64 * K;
@@ -534,7 +539,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         float4 *slot = &jacc[wv][0];
         const bool diag = (cur_delta == 0);
         if (!diag)
-            adj_ring_steps<K>(xk, wk, tile_xm, tile_wv, slot, lane, eps2, tk);
+            adj_ring_steps<K, HAS_V>(xk, wk, tile_xm, tile_wv, slot, lane, eps2, tk);
         else
             adj_tile_steps<K, true>(xk, wk, kk, tile_xm, tile_wv, slot, lane, wv * K, cur_u,
                                     cur_base, eps2, tk);
@@ -598,8 +603,8 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     constexpr int PB = W * 64 * K;
     const int M = (n + PB - 1) / PB;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_sym_kernel<W, K>,
-                                                                W * 64, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, backward_sym_kernel<W, K, true>, W * 64, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     int C = per_cu * dev.num_cu / (M * OCC);
@@ -613,7 +618,12 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     SymBwdArgs A{x, m, ga, gp, n, eps2, M, C, static_cast<float4 *>(ws)};
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
     prof_mark(stream, 0);
-    hipLaunchKernelGGL((backward_sym_kernel<W, K>), dim3(M * C), dim3(W * 64), 0, stream, A);
+    if (gp)
+        hipLaunchKernelGGL((backward_sym_kernel<W, K, true>), dim3(M * C), dim3(W * 64), 0, stream,
+                           A);
+    else
+        hipLaunchKernelGGL((backward_sym_kernel<W, K, false>), dim3(M * C), dim3(W * 64), 0,
+                           stream, A);
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;

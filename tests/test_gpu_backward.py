@@ -147,3 +147,17 @@ def test_pair_once_block_rings(nb, n):
             _check(gx1, gm1, rx1, rm1, f"{name} n={n} v only")
     finally:
         nb.set_variant(nb.BACKWARD, -1)
+
+
+@pytest.mark.parametrize("n", [16384, 70000])
+def test_no_potential_weights_kernel(nb, n):
+    # grad_p None takes the pair-once kernel that does not form the
+    # potential-weight terms; it must agree with explicit zero weights
+    dev = need_gpu()
+    x = to_dev(inputs.plummer_positions(n, (66, n)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (66, n, 1)), dev)
+    ga = to_dev(inputs.normal((n, 3), (66, n, 2)), dev)
+    assert nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, n)].startswith("bwd_sym")
+    gx0, gm0 = nb.forces_backward(x, m, 1e-4, ga, torch.zeros((n,), device=dev))
+    gx1, gm1 = nb.forces_backward(x, m, 1e-4, ga, None)
+    assert torch.equal(gx0, gx1) and torch.equal(gm0, gm1)
