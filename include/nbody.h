@@ -146,8 +146,10 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
  * Kernels: for 2^13 <= n <= 2^20 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair)
- * with about 8 n^2 / 1024 bytes of workspace; otherwise every ordered pair
- * is gathered per row.
+ * with about 8 n^2 / P bytes of workspace for blocks of P = 256 (below
+ * 2^16) or 1024 particles (8.6 GB at n = 2^20); with grad_p NULL it does
+ * not form the potential-weight terms (same result as zero weights).
+ * Otherwise every ordered pair is gathered per row.
  */
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
                                    const float *grad_a, const float *grad_p,
