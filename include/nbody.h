@@ -87,14 +87,14 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 12,288 <= n <= 2^21 the default variant evaluates each
+ * Kernels: for 5,000 <= n <= 2^21 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair); it needs about 8 n^2 / P bytes of
  * library workspace, with blocks of P = 4096 particles from 2^18 up
  * (2.1 GB at n = 2^20) and P = 2048 down to 256 below.  Outside that range the default
- * gathers every ordered pair per row with j-splits: below 2^13 in one launch
+ * gathers every ordered pair per row with j-splits: below 5,000 in one launch
  * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
- * workspace and one int counter per 64 rows), otherwise with float64 row
+ * workspace and one int counter per 64 rows), above 2^21 with float64 row
  * sums (as NBODY_FORCES_F64_SUM below) and a reduction launch (at most
  * 32 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
@@ -123,7 +123,7 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
  * float32 once at the store.  Float32 running sums add n / tile tile sums in
  * float32, an error that grows with n; the paper computes in single
  * precision throughout (Sec. IV).  The default already sums in float64
- * outside 12,288 <= n <= 2^21; inside that range the flag trades the
+ * outside 5,000 <= n <= 2^21; inside that range the flag trades the
  * pair-once kernel for the row gather (about 20% slower at n = 2^20) and
  * 32 n * splits bytes of workspace.  A forced variant (nbody_set_variant)
  * is honoured only if it is one of the "_f64sum" variants.

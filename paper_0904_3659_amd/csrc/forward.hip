@@ -405,10 +405,9 @@ static int variant_index(const char *name)
 // gather kernel, which needs no workspace at that size, takes over.
 int forward_default_variant(int64_t n)
 {
-    // The gathers keep float64 row sums: as fast as float32 sums here and
+    // The gather keeps float64 row sums: as fast as float32 sums and
     // 10-100x more accurate above a million bodies.
     static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
-    static const int gather_mid = variant_index("fwd_b256_k1_u8_f64sum");
     static const int one_launch = variant_index("fwd_la_w16");
     static const int pair_once_16 = variant_index("fwd_sym_w16_k4_o1");
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
@@ -420,8 +419,7 @@ int forward_default_variant(int64_t n)
     if (n >= (1 << 18)) return pair_once_16;
     if (n >= (1 << 17)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
-    if (n >= 3 * (1 << 12)) return pair_once_1;
-    if (n >= (1 << 13)) return gather_mid;
+    if (n >= 5000) return pair_once_1;
     // Small n is set by launch latency: one launch, no reduction kernel.
     return one_launch;
 }
