@@ -144,7 +144,7 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
  * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
- * Kernels: for 2^13 <= n <= 2^20 the default variant evaluates each
+ * Kernels: for 2^11 <= n <= 2^20 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair)
  * with about 8 n^2 / P bytes of workspace for blocks of P = 256 (below
  * 2^16) or 1024 particles (8.6 GB at n = 2^20); with grad_p NULL it does

@@ -691,13 +691,14 @@ static int variant_index(const char *name)
 int backward_default_variant(int64_t n)
 {
     static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
-    static const int pair_once_small = variant_index("bwd_sym_w2_k2_o1");
+    static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
+    static const int pair_once_small = variant_index("bwd_sym_w4_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
     if (n > (1 << 20)) return gather;
     if (n >= (1 << 16)) return pair_once;
-    if (n >= (1 << 13)) return pair_once_small;
-    if (n >= (1 << 11)) return gather;
+    if (n >= (1 << 13)) return pair_once_mid;
+    if (n >= (1 << 11)) return pair_once_small;
     return gather_small;
 }
 
