@@ -90,8 +90,8 @@ const char *nbody_last_error(void);
  * Kernels: for 5,000 <= n <= 2^21 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair); it needs about 8 n^2 / P bytes of
- * library workspace, with blocks of P = 4096 particles from 2^18 up
- * (2.1 GB at n = 2^20) and P = 2048 down to 256 below.  Outside that range the default
+ * library workspace, with blocks of P = 2048 particles from 2^17 up
+ * (4.3 GB at n = 2^20, 17 GB at 2^21) and P = 1024 or 256 below.  Outside that range the default
  * gathers every ordered pair per row with j-splits: below 5,000 in one launch
  * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
  * workspace and one int counter per 64 rows), above 2^21 with float64 row

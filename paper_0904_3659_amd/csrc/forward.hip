@@ -409,14 +409,13 @@ int forward_default_variant(int64_t n)
     // 10-100x more accurate above a million bodies.
     static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
     static const int one_launch = variant_index("fwd_la_w16");
-    static const int pair_once_16 = variant_index("fwd_sym_w16_k4_o1");
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_o1");
     static const int pair_once_1 = variant_index("fwd_sym_w1_k4_o1");
     if (n > (1 << 21)) return gather_big;
-    // 16-wave blocks (4,096 particles) above 2^18 also halve the partial
-    // workspace (8 n^2 / 4096 bytes: 2.1 GB at 2^20) against 8-wave ones
-    if (n >= (1 << 18)) return pair_once_16;
+    // 8-wave blocks of 2,048 particles, two workgroups per CU: 1% ahead of
+    // 16-wave blocks at 2^20 (same-box A/B, repeated); their partial
+    // workspace is 8 n^2 / 2048 bytes (4.3 GB at 2^20, 17 GB at 2^21)
     if (n >= (1 << 17)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
     if (n >= 5000) return pair_once_1;
