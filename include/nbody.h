@@ -12,16 +12,19 @@
  * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
  *   is asynchronous with respect to the host and ordered on `stream`; faults
  *   inside a kernel surface at the caller's next synchronisation.
- * - Outputs are fully overwritten, never accumulated into.  Inputs and
- *   outputs must not overlap (checked on the host from the address ranges).
+ * - Outputs are fully overwritten, never accumulated into, except the
+ *   in/out arrays of the element-wise and leap-frog calls (stated there).
+ *   Inputs and outputs must not overlap (checked on the host from the
+ *   address ranges).
  * - Library workspace (partial sums, work lists) is device memory owned by
  *   the library, cached per (device, stream) and grown on demand; it is held
  *   until nbody_release_workspace() or process exit.  Calls that share one
  *   stream reuse it safely; calls on different streams use different
  *   workspaces.
  * - HIP graph capture: nbody_forces, nbody_forces_ex, nbody_forces_backward,
- *   nbody_forces_batched, nbody_axpy and nbody_kick_drift may be captured on
- *   a stream once the same call has run eagerly on that stream (so that the
+ *   nbody_forces_batched, nbody_axpy, nbody_kick_drift, nbody_leapfrog and
+ *   nbody_leapfrog_adjoint may be captured on a stream once the same call
+ *   has run eagerly on that stream (so that the
  *   stream's workspace, counters and the batched plan exist; a first call
  *   allocates and a first batched call synchronises, which capture forbids).
  *   The graph keeps the workspace addresses of that stream: while it may
@@ -45,8 +48,9 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 2
+#define NBODY_ABI_VERSION 3
 #define NBODY_MAX_N (INT64_C(1) << 28)
+#define NBODY_MAX_STEPS (INT64_C(1) << 30)
 
 typedef enum nbody_status {
     NBODY_OK = 0,
@@ -199,6 +203,66 @@ nbody_status nbody_axpy(float *y, const float *xv, int64_t len, float alpha, voi
  */
 nbody_status nbody_kick_drift(float *x, float *v, const float *a, int64_t n, float kick, float dt,
                               void *stream);
+
+/*
+ * `steps` leap-frog (kick-drift-kick) steps on the device, Eqs. (1)-(3) of
+ * Sec. III with the physical acceleration -a (a in the paper's sign, as
+ * nbody_forces gives it) and no potential:
+ *     repeat steps times:  v += -dt/2 a;  x += dt v;  a = a(x);  v += -dt/2 a
+ * x, v: [n][3] in/out.  a: [n][3] in/out: a(x) on entry (nbody_forces with
+ * the same n and eps2), a of the final positions on exit.  m: [n] in.
+ * x_hist: NULL, or [steps][n][3] out: x_hist[t] receives the positions
+ * after step t + 1 (x_hist[steps - 1] equals x on exit).
+ * The result is bitwise that of the call sequence
+ *     nbody_kick_drift(x, v, a, n, -dt/2, dt);
+ *     nbody_forces(x, m, n, eps2, a, NULL);
+ *     nbody_axpy(v, a, 3 n, -dt/2);
+ * repeated steps times (the same float32 FMAs in the same order).  A
+ * step's end kick, the next step's start kick and its drift run in the
+ * final reduction kernel of the pair-once force variants (two launches per
+ * step), otherwise in one element-wise launch after the force.  Library
+ * memory: that of nbody_forces.
+ * Errors: n < 0 or > NBODY_MAX_N, steps < 0 or > NBODY_MAX_STEPS, eps2 as
+ * for nbody_forces, dt not finite, NULL x, v, a or m with n > 0 and
+ * steps > 0, any two of x, v, a, m, x_hist overlapping -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_leapfrog(float *x, float *v, float *a, const float *m, int64_t n, float eps2,
+                            float dt, int64_t steps, float *x_hist, void *stream);
+
+/* Flags of nbody_leapfrog_adjoint. */
+#define NBODY_LEAPFROG_FINAL 1u   /* the segment ends at the final state */
+#define NBODY_LEAPFROG_INITIAL 2u /* the segment starts at the initial state */
+
+/*
+ * Reverse sweep over one segment of `steps` nbody_leapfrog steps: the
+ * vector-Jacobian product of the steps with respect to the positions,
+ * velocities and masses (the adjoint of a checkpointed integration, one
+ * segment per call, last segment first).
+ * pos: [steps + 1][n][3] in, the positions the forward pass visited:
+ *   pos[0] at the segment's start, pos[t] after its t-th step.
+ * lx, lv: [n][3] in/out: dL/dx and dL/dv at the segment's end on entry,
+ *   at its start on exit.  lm: [n] in/out: dL/dm, accumulated (+=).
+ * Each kick is a VJP of Eq. (gravity) with weights lv on a
+ * (nbody_forces_backward with grad_a = lv, grad_p = NULL) added to lx and
+ * lm with the factor c of its kicks: at pos[t], 1 <= t < steps, the end
+ * kick of step t and the start kick of step t + 1 (c = -dt); at pos[0] the
+ * first start kick plus, without NBODY_LEAPFROG_INITIAL, the end kick of
+ * the step before the segment (c = -dt/2 with the flag, else -dt); at
+ * pos[steps] the last end kick, only with NBODY_LEAPFROG_FINAL (c = -dt/2;
+ * without the flag the next segment's sweep has covered it).  Order, from
+ * the segment's end: [final end kick,] then per step t = steps..1:
+ *     lv += dt lx;  lx += c VJP(pos[t-1])[lv];  lm += c VJP_m(pos[t-1])[lv]
+ * bitwise as that sequence of nbody_axpy and nbody_forces_backward calls.
+ * The updates run in the final reduction kernel of the pair-once adjoint
+ * variants (the next step's lv += dt lx with them).  Library memory: that
+ * of nbody_forces_backward plus 16 n bytes per (device, stream).
+ * Errors: unknown flag bits, n, steps, eps2 or dt as for nbody_leapfrog,
+ * NULL pos, m, lx, lv or lm with n > 0 and steps > 0, any two arrays
+ * overlapping -> INVALID_ARGUMENT.
+ */
+nbody_status nbody_leapfrog_adjoint(const float *pos, const float *m, int64_t n, float eps2,
+                                    float dt, int64_t steps, uint32_t flags, float *lx, float *lv,
+                                    float *lm, void *stream);
 
 /* ---------------------------------------------------------------- tuning */
 

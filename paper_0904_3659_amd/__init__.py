@@ -5,8 +5,9 @@ Importing the package loads nothing; the HIP library is loaded on first use
 by :mod:`paper_0904_3659_amd.nbody` and raises if it is missing.
 """
 
-__all__ = ["forces", "forces_backward", "forces_batched", "NBodyForces",
-           "leapfrog", "NBodyError"]
+# ``leapfrog`` names the submodule (the integrator); its entry point is
+# ``nbody.leapfrog`` or ``leapfrog.leapfrog``.
+__all__ = ["forces", "forces_backward", "forces_batched", "NBodyForces", "NBodyError"]
 
 
 def __getattr__(name):

@@ -598,7 +598,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 template <int W, int K, int OCC>
 nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
                               int n, float eps2, const float *ga, const float *gp, float *gx,
-                              float *gm, hipStream_t stream)
+                              float *gm, hipStream_t stream, const LfEpi *epi, bool *fused)
 {
     constexpr int PB = W * 64 * K;
     const int M = (n + PB - 1) / PB;
@@ -627,8 +627,14 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
-    hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
-                       A.partial, n, M, C, gx, gm);
+    if (epi && epi->mode != kLfNone) {
+        hipLaunchKernelGGL((slot_reduce_kernel<PB, true>), dim3((n + 63) / 64), dim3(256), 0,
+                           stream, A.partial, n, M, C, gx, gm, *epi);
+        if (fused) *fused = true;
+    } else {
+        hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
+                           A.partial, n, M, C, gx, gm, LfEpi{});
+    }
     return check_launch("slot_reduce");
 }
 
@@ -636,7 +642,7 @@ using KernelFn = void (*)(BwdArgs);
 
 using SymRunFn = nbody_status (*)(const char *, const Device &, const float *, const float *,
                                   int, float, const float *, const float *, float *, float *,
-                                  hipStream_t);
+                                  hipStream_t, const LfEpi *, bool *);
 
 // A gather variant (rows own all j) or, with sym set, a pair-once variant.
 struct Variant {
@@ -704,10 +710,11 @@ int backward_default_variant(int64_t n)
 
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m, int n,
                           float eps2, const float *ga, const float *gp, float *gx, float *gm,
-                          hipStream_t stream)
+                          hipStream_t stream, const LfEpi *epi, bool *fused)
 {
     const Variant &V = kVariants[variant];
-    if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream);
+    if (fused) *fused = false;
+    if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream, epi, fused);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     const int target = 4 * dev.num_cu;

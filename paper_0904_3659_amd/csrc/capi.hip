@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -114,14 +115,14 @@ struct Buffer {
     size_t bytes = 0;
 };
 std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, Buffer> g_ws;
-}  // namespace
+// (device, stream, 0 for workspace() or 1 for workspace_aux())
+std::map<std::tuple<int, hipStream_t, int>, Buffer> g_ws;
 
-nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr)
+nbody_status grow_buffer(const Device &dev, hipStream_t stream, int slot, size_t bytes, void **ptr)
 {
     if (fault_injected("alloc")) return fail(NBODY_ERROR_OUT_OF_MEMORY, "injected allocation fault");
     std::lock_guard<std::mutex> lock(g_ws_mu);
-    Buffer &b = g_ws[{dev.id, stream}];
+    Buffer &b = g_ws[{dev.id, stream, slot}];
     if (b.bytes < bytes) {
         if (b.ptr) {
             // hipFree waits for the device, so kernels still reading the old
@@ -141,6 +142,17 @@ nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void
     }
     *ptr = b.ptr;
     return NBODY_OK;
+}
+}  // namespace
+
+nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr)
+{
+    return grow_buffer(dev, stream, 0, bytes, ptr);
+}
+
+nbody_status workspace_aux(const Device &dev, hipStream_t stream, size_t bytes, void **ptr)
+{
+    return grow_buffer(dev, stream, 1, bytes, ptr);
 }
 
 namespace {
@@ -538,6 +550,131 @@ nbody_status nbody_kick_drift(float *x, float *v, const float *a, int64_t n, flo
     return kick_drift_run(x, v, a, 3 * n, kick, dt, (hipStream_t)stream);
 }
 
+nbody_status nbody_leapfrog(float *x, float *v, float *a, const float *m, int64_t n, float eps2,
+                            float dt, int64_t steps, float *x_hist, void *stream)
+{
+    clear_error();
+    if (n < 0 || n > NBODY_MAX_N)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld outside [0, %lld]", (long long)n,
+                    (long long)NBODY_MAX_N);
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    if (!std::isfinite(dt)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "dt is not finite");
+    if (steps < 0 || steps > NBODY_MAX_STEPS)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]", (long long)steps,
+                    (long long)NBODY_MAX_STEPS);
+    if (n == 0 || steps == 0) return NBODY_OK;
+    if (!x || !v || !a || !m)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x, v, a or m with n = %lld", (long long)n);
+    const size_t v3 = 12 * (size_t)n, v1 = 4 * (size_t)n;
+    const void *arr[5] = {x, v, a, m, x_hist};
+    const size_t len[5] = {v3, v3, v3, v1, v3 * (size_t)steps};
+    for (int i = 0; i < 5; ++i)
+        for (int k = i + 1; k < 5; ++k)
+            if (overlaps(arr[i], len[i], arr[k], len[k]))
+                return fail(NBODY_ERROR_INVALID_ARGUMENT, "x, v, a, m and x_hist must not overlap");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    const int variant = select_variant(NBODY_KIND_FORWARD, n);
+    const float kick = -0.5f * dt;  // half kick with the physical acceleration -a
+    // start kick and drift of the first step
+    LfEpi e;
+    e.mode = kLfKick;
+    e.kicks = 1;
+    e.drift = 1;
+    e.k1 = kick;
+    e.k2 = kick;
+    e.dt = dt;
+    e.v = v;
+    e.x = x;
+    e.xh = x_hist;
+    st = lf_epilogue_run(a, nullptr, n, e, s);
+    for (int64_t t = 0; t < steps && st == NBODY_OK; ++t) {
+        // a(x) of this step, its end kick and, unless it is the last step,
+        // the next step's start kick and drift
+        const bool last = t == steps - 1;
+        e.kicks = last ? 1 : 2;
+        e.drift = last ? 0 : 1;
+        e.xh = (!last && x_hist) ? x_hist + 3 * (size_t)n * (size_t)(t + 1) : nullptr;
+        bool fused = false;
+        st = forward_run(variant, dev, x, m, (int)n, eps2, a, nullptr, s, &e, &fused);
+        if (st == NBODY_OK && !fused) st = lf_epilogue_run(a, nullptr, n, e, s);
+        if (st == NBODY_OK) prof_mark(s, 2);
+    }
+    return st;
+}
+
+nbody_status nbody_leapfrog_adjoint(const float *pos, const float *m, int64_t n, float eps2,
+                                    float dt, int64_t steps, uint32_t flags, float *lx, float *lv,
+                                    float *lm, void *stream)
+{
+    clear_error();
+    const uint32_t known = NBODY_LEAPFROG_FINAL | NBODY_LEAPFROG_INITIAL;
+    if (flags & ~known)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "unknown flag bits 0x%x", (unsigned)(flags & ~known));
+    if (n < 0 || n > NBODY_MAX_N)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "n = %lld outside [0, %lld]", (long long)n,
+                    (long long)NBODY_MAX_N);
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    if (!std::isfinite(dt)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "dt is not finite");
+    if (steps < 0 || steps > NBODY_MAX_STEPS)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]", (long long)steps,
+                    (long long)NBODY_MAX_STEPS);
+    if (n == 0 || steps == 0) return NBODY_OK;
+    if (!pos || !m || !lx || !lv || !lm)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL pos, m, lx, lv or lm with n = %lld", (long long)n);
+    const size_t v3 = 12 * (size_t)n, v1 = 4 * (size_t)n;
+    const void *arr[5] = {pos, m, lx, lv, lm};
+    const size_t len[5] = {v3 * (size_t)(steps + 1), v1, v3, v3, v1};
+    for (int i = 0; i < 5; ++i)
+        for (int k = i + 1; k < 5; ++k)
+            if (overlaps(arr[i], len[i], arr[k], len[k]))
+                return fail(NBODY_ERROR_INVALID_ARGUMENT, "pos, m, lx, lv and lm must not overlap");
+    Device dev;
+    nbody_status st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    const int variant = select_variant(NBODY_KIND_BACKWARD, n);
+    // VJP results of variants that cannot take the update in their final
+    // reduction
+    void *aux = nullptr;
+    st = workspace_aux(dev, s, 16 * (size_t)n, &aux);
+    if (st != NBODY_OK) return st;
+    float *gx = static_cast<float *>(aux);
+    float *gm = gx + 3 * (size_t)n;
+    LfEpi e;
+    e.mode = kLfAdjoint;
+    e.dt = dt;
+    e.lx = lx;
+    e.lm = lm;
+    e.lv = lv;
+    // lx, lm += c VJP(positions)[lv]; then lv += dt lx if `chain`
+    auto vjp = [&](const float *xp, float c, bool chain) {
+        e.c = c;
+        e.chain = chain ? 1 : 0;
+        bool fused = false;
+        nbody_status r = backward_run(variant, dev, xp, m, (int)n, eps2, lv, nullptr, gx, gm, s,
+                                      &e, &fused);
+        if (r == NBODY_OK && !fused) r = lf_epilogue_run(gx, gm, n, e, s);
+        if (r == NBODY_OK) prof_mark(s, 2);
+        return r;
+    };
+    const float half = 0.5f * dt;
+    const size_t stride = 3 * (size_t)n;
+    if (flags & NBODY_LEAPFROG_FINAL)
+        st = vjp(pos + stride * (size_t)steps, -half, true);  // end kick of the last step
+    else
+        st = axpy_run(lv, lx, 3 * n, dt, s);  // drift of the segment's last step
+    for (int64_t t = steps; t >= 1 && st == NBODY_OK; --t) {
+        // positions before step t of the segment: its start kick, plus the
+        // end kick of the step before at the same positions (none at step 0)
+        const bool first = (flags & NBODY_LEAPFROG_INITIAL) && t == 1;
+        st = vjp(pos + stride * (size_t)(t - 1), first ? -half : -dt, t > 1);
+    }
+    return st;
+}
+
 int nbody_variant_count(int kind) { return variant_count(kind); }
 
 const char *nbody_variant_name(int kind, int index) { return variant_name(kind, index); }
@@ -570,7 +707,7 @@ nbody_status nbody_release_workspace(void)
         if (kv.second.ptr) {
             int cur = -1;
             (void)hipGetDevice(&cur);
-            (void)hipSetDevice(kv.first.first);
+            (void)hipSetDevice(std::get<0>(kv.first));
             hipError_t e = hipFree(kv.second.ptr);
             (void)hipSetDevice(cur);
             if (e != hipSuccess && st == NBODY_OK) st = hip_fail(e, "hipFree(workspace)");

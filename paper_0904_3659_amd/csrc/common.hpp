@@ -9,6 +9,7 @@
 #include <cstdint>
 
 #include "../../include/nbody.h"
+#include "leapfrog_epi.hpp"
 
 namespace nbody {
 
@@ -33,6 +34,10 @@ nbody_status current_device(Device *dev);
 // valid until the next workspace() call on the same (device, stream) that
 // asks for more bytes, or nbody_release_workspace().
 nbody_status workspace(const Device &dev, hipStream_t stream, size_t bytes, void **ptr);
+// A second buffer of the same kind (same lifetime rules), for callers that
+// keep data across calls that use workspace() (the leap-frog adjoint's
+// unfused VJP results).
+nbody_status workspace_aux(const Device &dev, hipStream_t stream, size_t bytes, void **ptr);
 
 // Per-(device, stream) array of at least `count` int counters that are zero
 // between calls (kernels that use them leave them at zero); zero-filled
@@ -66,21 +71,29 @@ const char *forward_variant_name(int index);
 int forward_default_variant(int64_t n);
 bool forward_variant_f64sum(int variant);
 int forward_default_f64sum_variant(int64_t n);
+// With `epi` (mode != kLfNone) the leap-frog update follows the store of a:
+// inside the final reduction kernel where the variant has one that can take
+// it (*fused = true), otherwise not at all (*fused = false; the caller then
+// runs lf_epilogue_run).
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m,
-                         int n, float eps2, float *a, float *p, hipStream_t stream);
+                         int n, float eps2, float *a, float *p, hipStream_t stream,
+                         const LfEpi *epi = nullptr, bool *fused = nullptr);
 
 // Pair-once forward kernel (forward_sym.hip) with W waves and K rows/lane.
 nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
                              const float *x, const float *m, int n, float eps2, float *a, float *p,
-                             hipStream_t stream);
+                             hipStream_t stream, const LfEpi *epi = nullptr, bool *fused = nullptr);
 
 // ---- backward (vector-Jacobian product of Eq. (gravity))
 int backward_variant_count();
 const char *backward_variant_name(int index);
 int backward_default_variant(int64_t n);
+// `epi` / `fused` as for forward_run (kLfAdjoint updates; gx, gm still
+// receive the result when the update is not fused).
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m,
                           int n, float eps2, const float *ga, const float *gp,
-                          float *gx, float *gm, hipStream_t stream);
+                          float *gx, float *gm, hipStream_t stream,
+                          const LfEpi *epi = nullptr, bool *fused = nullptr);
 
 // ---- batched independent systems
 int batched_variant_count();
@@ -94,6 +107,10 @@ nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,
 nbody_status axpy_run(float *y, const float *xv, int64_t len, float alpha, hipStream_t stream);
 nbody_status kick_drift_run(float *x, float *v, const float *a, int64_t len, float kick, float dt,
                             hipStream_t stream);
+// The update `e` for n rows whose result is in r3[n][3] (and r1[n], may be
+// NULL): the unfused form of the epilogue of forward_run / backward_run.
+nbody_status lf_epilogue_run(const float *r3, const float *r1, int64_t n, const LfEpi &e,
+                             hipStream_t stream);
 // Zero len ints with a fill kernel on `stream` (no hipMemsetAsync, so the
 // work can sit in a captured graph).
 nbody_status fill_zero_int(int *p, size_t len, hipStream_t stream);

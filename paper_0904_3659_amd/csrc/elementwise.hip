@@ -31,6 +31,19 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(float *__restrict__ x,
     }
 }
 
+// The leap-frog update of `e` for rows whose force (or VJP) result is
+// already stored in r3 / r1: the unfused form of the reduction epilogue.
+__global__ __launch_bounds__(256) void lf_epilogue_kernel(const float *__restrict__ r3,
+                                                          const float *__restrict__ r1, int n,
+                                                          LfEpi e)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const float4 r = make_float4(r3[3 * (size_t)j + 0], r3[3 * (size_t)j + 1],
+                                 r3[3 * (size_t)j + 2], r1 ? r1[j] : 0.f);
+    lf_finish(e, j, r, nullptr, nullptr);
+}
+
 // 32-bit integer hash (Wang/Jenkins-style mixing) -> uniform float in [0,1).
 __device__ __forceinline__ float hash_unit(uint32_t v)
 {
@@ -95,6 +108,15 @@ nbody_status kick_drift_run(float *x, float *v, const float *a, int64_t len, flo
     hipLaunchKernelGGL(kick_drift_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, v, a, len,
                        kick, dt);
     return check_launch("kick_drift");
+}
+
+nbody_status lf_epilogue_run(const float *r3, const float *r1, int64_t n, const LfEpi &e,
+                             hipStream_t stream)
+{
+    if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+    hipLaunchKernelGGL(lf_epilogue_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       r3, r1, (int)n, e);
+    return check_launch("lf_epilogue");
 }
 
 nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint32_t seed,

@@ -399,10 +399,10 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once kernel wins from about 2^15 particles
-// on (W = 16 waves above 2^17); its partial buffer grows as 8 n^2 / P bytes
-// (P = 2048 or 4096 particles per block), so beyond 2^21 particles the
-// gather kernel, which needs no workspace at that size, takes over.
+// Measured on MI355X: the pair-once kernel wins from about 5,000 particles
+// on; its partial buffer grows as 8 n^2 / P bytes (P = 256 to 2048
+// particles per block), so beyond 2^21 particles the gather kernel, which
+// needs no workspace at that size, takes over.
 int forward_default_variant(int64_t n)
 {
     // The gather keeps float64 row sums: as fast as float32 sums and
@@ -445,9 +445,11 @@ static int choose_splits(int n, int iblocks, int tile, int num_cu)
 }
 
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m, int n,
-                         float eps2, float *a, float *p, hipStream_t stream)
+                         float eps2, float *a, float *p, hipStream_t stream, const LfEpi *epi,
+                         bool *fused)
 {
     const Variant &V = kVariants[variant];
+    if (fused) *fused = false;
     if (V.la_w) {
         // Waves per row block: about 4096 waves over the chip (4 per SIMD),
         // at least 32 j per wave, at most n / 32 waves.
@@ -475,7 +477,8 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
         return check_launch(V.name);
     }
     if (V.sym_w)
-        return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream);
+        return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream,
+                               epi, fused);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     int splits = choose_splits(n, iblocks, V.block, dev.num_cu);

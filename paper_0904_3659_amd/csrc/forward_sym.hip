@@ -32,7 +32,8 @@ __global__ __launch_bounds__(W * 64) void forward_sym_kernel(SymArgs A)
 // tail imbalance at small n, lower occupancy).
 template <int W, int K, int OCC>
 nbody_status run_sym(const char *name, const Device &dev, const float *x, const float *m, int n,
-                     float eps2, float *a, float *p, hipStream_t stream)
+                     float eps2, float *a, float *p, hipStream_t stream, const LfEpi *epi,
+                     bool *fused)
 {
     constexpr int PB = W * 64 * K;
     const int M = (n + PB - 1) / PB;
@@ -64,8 +65,14 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     prof_mark(stream, 1);
     st = check_launch(name);
     if (st != NBODY_OK) return st;
-    hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
-                       A.partial, n, M, C, a, p);
+    if (epi && epi->mode != kLfNone) {
+        hipLaunchKernelGGL((slot_reduce_kernel<PB, true>), dim3((n + 63) / 64), dim3(256), 0,
+                           stream, A.partial, n, M, C, a, p, *epi);
+        if (fused) *fused = true;
+    } else {
+        hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
+                           A.partial, n, M, C, a, p, LfEpi{});
+    }
     return check_launch("slot_reduce");
 }
 
@@ -73,17 +80,17 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
 
 nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
                              const float *x, const float *m, int n, float eps2, float *a, float *p,
-                             hipStream_t stream)
+                             hipStream_t stream, const LfEpi *epi, bool *fused)
 {
-    if (W == 8 && K == 4 && occ == 1) return run_sym<8, 4, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 8 && K == 4 && occ == 2) return run_sym<8, 4, 2>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 4 && K == 8 && occ == 1) return run_sym<4, 8, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 4 && K == 4 && occ == 1) return run_sym<4, 4, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 2 && K == 8 && occ == 1) return run_sym<2, 8, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 1 && K == 8 && occ == 1) return run_sym<1, 8, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 16 && K == 4 && occ == 1) return run_sym<16, 4, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 2 && K == 4 && occ == 1) return run_sym<2, 4, 1>(name, dev, x, m, n, eps2, a, p, stream);
-    if (W == 1 && K == 4 && occ == 1) return run_sym<1, 4, 1>(name, dev, x, m, n, eps2, a, p, stream);
+    if (W == 8 && K == 4 && occ == 1) return run_sym<8, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 8 && K == 4 && occ == 2) return run_sym<8, 4, 2>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 4 && K == 8 && occ == 1) return run_sym<4, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 4 && K == 4 && occ == 1) return run_sym<4, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 2 && K == 8 && occ == 1) return run_sym<2, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 1 && K == 8 && occ == 1) return run_sym<1, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 16 && K == 4 && occ == 1) return run_sym<16, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 2 && K == 4 && occ == 1) return run_sym<2, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
+    if (W == 1 && K == 4 && occ == 1) return run_sym<1, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     return fail(NBODY_ERROR_INTERNAL, "no pair-once forward kernel for W=%d K=%d occ=%d", W, K, occ);
 }
 

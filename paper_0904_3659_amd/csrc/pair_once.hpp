@@ -76,10 +76,11 @@ __host__ __device__ __forceinline__ int ring_in(int J, int M)
 // added in group order: a fixed order (bitwise reproducible) with four times
 // the parallelism of one thread per particle.  xyz goes to out3[j][3], w to
 // out1[j] (skipped when out1 is NULL).  A workgroup covers 64 particles.
-template <int PB>
+// With EPI the leap-frog update `e` follows the store (leapfrog_epi.hpp).
+template <int PB, bool EPI = false>
 __global__ __launch_bounds__(256) void slot_reduce_kernel(const float4 *__restrict__ partial,
                                                           int n, int M, int C, float *out3,
-                                                          float *out1)
+                                                          float *out1, LfEpi e)
 {
     __shared__ float4 red[4][64];
     const int l = threadIdx.x & 63;
@@ -111,10 +112,14 @@ __global__ __launch_bounds__(256) void slot_reduce_kernel(const float4 *__restri
         t.z += v.z;
         t.w += v.w;
     }
-    out3[3 * j + 0] = t.x;
-    out3[3 * j + 1] = t.y;
-    out3[3 * j + 2] = t.z;
-    if (out1) out1[j] = t.w;
+    if constexpr (EPI) {
+        lf_finish(e, j, t, out3, out1);
+    } else {
+        out3[3 * j + 0] = t.x;
+        out3[3 * j + 1] = t.y;
+        out3[3 * j + 2] = t.z;
+        if (out1) out1[j] = t.w;
+    }
 }
 
 // Tile u of block I's sequence: the TPB diagonal tiles (delta 0), then the

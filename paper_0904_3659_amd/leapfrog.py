@@ -4,10 +4,11 @@ The integrator is the kick-drift-kick scheme of Eqs. (1)-(3) with the
 seven-step algorithm of Sec. III: one force evaluation per step, reused by
 the next step's first kick.  The paper's a (Eq. (gravity)) points away from
 the attracting body, so the physical acceleration is g = -a and a kick is
-v += (dt/2) g = v - (dt/2) a.  Every step is a library call: the force
-evaluation (``nbody_forces``), its adjoint (``nbody_forces_backward``) and
-the kick/drift updates (``nbody_kick_drift``, ``nbody_axpy``); tensors only
-hold device memory.
+v += (dt/2) g = v - (dt/2) a.  A run of steps is one library call
+(``nbody_leapfrog``): per step the force kernel, then a reduction whose
+epilogue applies the step's end kick, the next step's start kick and its
+drift; the reverse sweep over a segment is one ``nbody_leapfrog_adjoint``
+call in the same way.  Tensors only hold device memory.
 
 Reverse sweep for a loss on the final state.  With adjoints (lx, lv) of the
 step output (x_t, v_t), stepping back over step t-1 is
@@ -24,10 +25,10 @@ checkpoint before sweeping it.  The kernels are deterministic, so the
 recomputed positions and hence the gradients are bitwise equal to those of a
 run that stores every position.
 
-HIP graphs: a k-step segment (3k launches), the recomputation of a
+HIP graphs: a k-step segment (2k + 1 launches), the recomputation of a
 segment's positions and the reverse sweep over an interior segment are each
 captured once as a HIP graph on fixed device buffers and replayed once per
-segment, instead of issuing every launch from Python.  The graphs run the
+segment, instead of issuing every launch from the host.  The graphs run the
 same kernels on the same data, so results are bitwise equal to the eager
 path (``graphs=False``).
 """
@@ -37,13 +38,6 @@ from __future__ import annotations
 import torch
 
 from . import nbody as _nb
-
-
-def _step(x, v, a, m, eps2, dt):
-    """One KDK step in place; `a` holds a(x) on entry and a(x') on exit."""
-    _nb.kick_drift_(x, v, a, -0.5 * dt, dt)      # Eqs. (1)-(2)
-    _nb.forces(x, m, eps2, out=(a, None), potential=False)
-    _nb.axpy_(v, a, -0.5 * dt)                   # Eq. (3)
 
 
 def _last_start(steps: int, k: int) -> int:
@@ -57,82 +51,69 @@ def integrate(x0, v0, m, eps2, dt, steps, *, keep_every: int | None = None):
     Returns (x_T, v_T, saved).  With ``keep_every=k``, ``saved[t]`` is a
     copy of (x, v, a) at every step t that is a multiple of k and at
     t = steps, and ``saved["tail"]`` holds the positions of the last
-    segment (x at its first step .. x_T), which the reverse sweep then need
-    not recompute.  Without it ``saved`` is {}.
+    segment ([steps - last + 1, n, 3]: x at its first step .. x_T), which
+    the reverse sweep then need not recompute.  Without it ``saved`` is {}.
     """
     x = x0.detach().clone().contiguous()
     v = v0.detach().clone().contiguous()
     a, _ = _nb.forces(x, m, eps2, potential=False)
     saved = {}
-    last = _last_start(steps, keep_every) if keep_every and steps > 0 else None
-    tail = []
-    for t in range(steps):
-        if keep_every and t % keep_every == 0:
-            saved[t] = (x.clone(), v.clone(), a.clone())
-        if t == last:
-            tail.append(x.clone())
-        _step(x, v, a, m, eps2, dt)
-        if last is not None and t >= last:
-            tail.append(x.clone())
-    if keep_every:
-        saved[steps] = (x.clone(), v.clone(), a.clone())
-        saved["tail"] = tail
+    if not keep_every:
+        _nb.leapfrog_(x, v, a, m, eps2, dt, steps)
+        return x, v, saved
+    last = _last_start(steps, keep_every) if steps > 0 else None
+    for s0 in range(0, steps, keep_every):
+        count = min(keep_every, steps - s0)
+        saved[s0] = (x.clone(), v.clone(), a.clone())
+        if s0 == last:
+            tail = torch.empty((count + 1,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+            tail[0].copy_(x)
+            _nb.leapfrog_(x, v, a, m, eps2, dt, count, x_hist=tail[1:])
+            saved["tail"] = tail
+        else:
+            _nb.leapfrog_(x, v, a, m, eps2, dt, count)
+    saved[steps] = (x.clone(), v.clone(), a.clone())
     return x, v, saved
 
 
 def _positions(xs, vs, a0, m, eps2, dt, count):
-    """Positions after 0..count steps from (xs, vs) with a0 = a(xs)."""
-    x = xs.clone()
-    v = vs.clone()
-    a = a0.clone()
-    out = [x.clone()]
-    for _ in range(count):
-        _step(x, v, a, m, eps2, dt)
-        out.append(x.clone())
-    return out
+    """Positions [count + 1, n, 3] after 0..count steps from (xs, vs) with
+    a0 = a(xs)."""
+    pos = torch.empty((count + 1,) + tuple(xs.shape), dtype=xs.dtype, device=xs.device)
+    pos[0].copy_(xs)
+    _nb.leapfrog_(xs.clone(), vs.clone(), a0.clone(), m, eps2, dt, count, x_hist=pos[1:])
+    return pos
 
 
-def _sweep_segment(pos, s0, s1, m, eps2, dt, lx, lv, lm, gxw, gmw):
-    """Reverse over steps s1-1 .. s0 with positions pos[0..s1-s0]."""
-    half = 0.5 * dt
-    for t in range(s1, s0, -1):
-        _nb.axpy_(lv, lx, dt)                            # drift of step t-1
-        c = -dt if t - 1 > 0 else -half                   # start kick of t-1 (+ end kick of t-2)
-        _nb.forces_backward(pos[t - 1 - s0], m, eps2, lv, None, out=(gxw, gmw))
-        _nb.axpy_(lx, gxw, c)
-        _nb.axpy_(lm, gmw, c)
-
-
-def _end_kick(pos_T, m, eps2, dt, lx, lv, lm, gxw, gmw):
-    """The last step's end kick, weight lv_T."""
-    _nb.forces_backward(pos_T, m, eps2, lv, None, out=(gxw, gmw))
-    _nb.axpy_(lx, gxw, -0.5 * dt)
-    _nb.axpy_(lm, gmw, -0.5 * dt)
+def _flags(s0: int, last: int, final_kick: bool) -> int:
+    f = _nb.LEAPFROG_INITIAL if s0 == 0 else 0
+    if s0 == last and final_kick:
+        f |= _nb.LEAPFROG_FINAL
+    return f
 
 
 def reverse_sweep(saved, m, eps2, dt, steps, gx_T, gv_T, checkpoint_every):
-    """Adjoints (dL/dx0, dL/dv0, dL/dm) from the output adjoints (gx_T, gv_T)."""
+    """Adjoints (dL/dx0, dL/dv0, dL/dm) from the output adjoints (gx_T, gv_T).
+
+    Without gv_T the final end kick carries zero weight and is skipped."""
     dev = m.device
     n = m.shape[0]
     lx = gx_T.detach().clone().contiguous() if gx_T is not None else torch.zeros((n, 3), device=dev)
     lv = gv_T.detach().clone().contiguous() if gv_T is not None else torch.zeros((n, 3), device=dev)
     lm = torch.zeros((n,), device=dev)
-    gxw = torch.empty((n, 3), device=dev)
-    gmw = torch.empty((n,), device=dev)
     if steps == 0:
         return lx, lv, lm
     k = checkpoint_every
     last = _last_start(steps, k)
     for s0 in reversed(range(0, steps, k)):
-        s1 = min(s0 + k, steps)
+        count = min(k, steps - s0)
         if s0 == last:
             pos = saved["tail"]                          # kept by the forward pass
-            if gv_T is not None:
-                _end_kick(pos[-1], m, eps2, dt, lx, lv, lm, gxw, gmw)
         else:
             xs, vs, a0 = saved[s0]
-            pos = _positions(xs, vs, a0, m, eps2, dt, s1 - s0)  # x_{s0} .. x_{s1}
-        _sweep_segment(pos, s0, s1, m, eps2, dt, lx, lv, lm, gxw, gmw)
+            pos = _positions(xs, vs, a0, m, eps2, dt, count)  # x_{s0} .. x_{s0+count}
+        _nb.leapfrog_adjoint_(pos, m, eps2, dt, lx, lv, lm,
+                              flags=_flags(s0, last, gv_T is not None))
     return lx, lv, lm
 
 
@@ -141,8 +122,8 @@ class SegmentGraphs:
 
     ``fwd``  k steps on (x, v, a), with a = a(x) on entry and exit;
     ``pos``  k steps from (pos[0], pv, pa), keeping pos[1..k];
-    ``rev``  the reverse sweep over an interior segment (global step > 0):
-             for local t = k..1: lv += dt lx; lx, lm -= dt VJP(pos[t-1])[lv].
+    ``rev``  the reverse sweep over an interior segment (global step > 0)
+             with positions pos[0..k].
 
     Each graph is captured on a stream of its own after one eager run there,
     so the library workspace its kernels point at belongs to that stream and
@@ -156,25 +137,22 @@ class SegmentGraphs:
         z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=dev)
         self.m, self.eps2, self.dt, self.k = m, eps2, dt, k
         self.x, self.v, self.a = z(n, 3), z(n, 3), z(n, 3)
-        self.pos = [z(n, 3) for _ in range(k + 1)]
-        self.pv, self.pa = z(n, 3), z(n, 3)
+        self.pos = z(k + 1, n, 3)
+        self.px, self.pv, self.pa = z(n, 3), z(n, 3), z(n, 3)
         self.lx, self.lv, self.lm = z(n, 3), z(n, 3), z(n)
-        self.gxw, self.gmw = z(n, 3), z(n)
         self._graphs = {name: self._capture(fn, dev)
                         for name, fn in (("fwd", self._fwd), ("pos", self._pos), ("rev", self._rev))}
 
     def _fwd(self):
-        for _ in range(self.k):
-            _step(self.x, self.v, self.a, self.m, self.eps2, self.dt)
+        _nb.leapfrog_(self.x, self.v, self.a, self.m, self.eps2, self.dt, self.k)
 
     def _pos(self):
-        for i in range(self.k):
-            self.pos[i + 1].copy_(self.pos[i])
-            _step(self.pos[i + 1], self.pv, self.pa, self.m, self.eps2, self.dt)
+        self.px.copy_(self.pos[0])
+        _nb.leapfrog_(self.px, self.pv, self.pa, self.m, self.eps2, self.dt, self.k,
+                      x_hist=self.pos[1:])
 
     def _rev(self):
-        _sweep_segment(self.pos, 1, 1 + self.k, self.m, self.eps2, self.dt,
-                       self.lx, self.lv, self.lm, self.gxw, self.gmw)
+        _nb.leapfrog_adjoint_(self.pos, self.m, self.eps2, self.dt, self.lx, self.lv, self.lm)
 
     @staticmethod
     def _capture(fn, dev):
@@ -192,7 +170,8 @@ class SegmentGraphs:
         self._graphs[name][0].replay()
 
     def segment_positions(self, xs, vs, a0):
-        """pos[0..k] from (xs, vs, a0 = a(xs)) by one replay."""
+        """pos[0..k] from (xs, vs, a0 = a(xs)) by one replay; (pv, pa) then
+        hold (v, a) after the k steps."""
         self.pos[0].copy_(xs)
         self.pv.copy_(vs)
         self.pa.copy_(a0)
@@ -231,15 +210,15 @@ def integrate_graphs(G: SegmentGraphs, x0, v0, steps: int):
             G.replay("fwd")
         elif steps - t == k:                 # a full last segment: keep its positions
             pos = G.segment_positions(G.x, G.v, G.a)
-            saved["tail"] = [p.clone() for p in pos]
+            saved["tail"] = pos.clone()
             G.x.copy_(pos[k])
             G.v.copy_(G.pv)
             G.a.copy_(G.pa)
         else:
-            tail = [G.x.clone()]
-            for _ in range(steps - t):
-                _step(G.x, G.v, G.a, G.m, G.eps2, G.dt)
-                tail.append(G.x.clone())
+            count = steps - t
+            tail = torch.empty((count + 1,) + tuple(G.x.shape), dtype=G.x.dtype, device=G.x.device)
+            tail[0].copy_(G.x)
+            _nb.leapfrog_(G.x, G.v, G.a, G.m, G.eps2, G.dt, count, x_hist=tail[1:])
             saved["tail"] = tail
     saved[steps] = (G.x.clone(), G.v.clone(), G.a.clone())
     return G.x.clone(), G.v.clone(), saved
@@ -261,18 +240,15 @@ def reverse_sweep_graphs(G: SegmentGraphs, saved, steps, gx_T, gv_T):
     lm.zero_()
     last = _last_start(steps, k)
     for s0 in reversed(range(0, steps, k)):
-        s1 = min(s0 + k, steps)
         if s0 == last:
             pos = saved["tail"]
-            if gv_T is not None:
-                _end_kick(pos[-1], m, eps2, dt, lx, lv, lm, G.gxw, G.gmw)
         else:
-            xs, vs, a0 = saved[s0]
-            pos = G.segment_positions(xs, vs, a0)    # interior segments are full
+            pos = G.segment_positions(*saved[s0])    # interior segments are full
             if s0 > 0:
                 G.replay("rev")
                 continue
-        _sweep_segment(pos, s0, s1, m, eps2, dt, lx, lv, lm, G.gxw, G.gmw)
+        _nb.leapfrog_adjoint_(pos, m, eps2, dt, lx, lv, lm,
+                              flags=_flags(s0, last, gv_T is not None))
     return lx.clone(), lv.clone(), lm.clone()
 
 

@@ -20,7 +20,7 @@ import torch
 from . import build as _build
 
 FORWARD, BACKWARD, BATCHED = 0, 1, 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _STATUS = {
     0: "NBODY_OK",
@@ -63,6 +63,9 @@ def lib() -> ctypes.CDLL:
         L.nbody_forces_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp, _vp, _vp]
         L.nbody_axpy.argtypes = [_vp, _vp, _i64, _f32, _vp]
         L.nbody_kick_drift.argtypes = [_vp, _vp, _vp, _i64, _f32, _f32, _vp]
+        L.nbody_leapfrog.argtypes = [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _i64, _vp, _vp]
+        L.nbody_leapfrog_adjoint.argtypes = [_vp, _vp, _i64, _f32, _f32, _i64, ctypes.c_uint32,
+                                             _vp, _vp, _vp, _vp]
         L.nbody_variant_count.argtypes = [ctypes.c_int]
         L.nbody_variant_count.restype = ctypes.c_int
         L.nbody_variant_name.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -77,7 +80,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_selected_variant.restype = ctypes.c_int
         for f in ("nbody_forces", "nbody_forces_ex", "nbody_forces_backward", "nbody_forces_batched",
                   "nbody_axpy",
-                  "nbody_kick_drift",
+                  "nbody_kick_drift", "nbody_leapfrog", "nbody_leapfrog_adjoint",
                   "nbody_set_variant", "nbody_autotune", "nbody_release_workspace",
                   "nbody_profile_enable", "nbody_profile_read"):
             getattr(L, f).restype = ctypes.c_int
@@ -246,6 +249,55 @@ def kick_drift_(x: torch.Tensor, v: torch.Tensor, a: torch.Tensor, kick: float, 
     return x, v
 
 
+LEAPFROG_FINAL = 1    # NBODY_LEAPFROG_FINAL
+LEAPFROG_INITIAL = 2  # NBODY_LEAPFROG_INITIAL
+
+
+def _steps(steps) -> int:
+    s = int(steps)
+    if s < 0:
+        raise ValueError(f"steps must be >= 0, got {steps}")
+    return s
+
+
+def leapfrog_(x, v, a, m, eps2: float, dt: float, steps: int, *, x_hist=None):
+    """In place: ``steps`` kick-drift-kick steps of (x, v) on the device
+    (nbody_leapfrog), with a = a(x) in the paper's sign on entry and exit.
+    ``x_hist`` ([steps, n, 3]) receives the positions after each step."""
+    n = int(m.shape[0]) if m.dim() == 1 else -1
+    steps = _steps(steps)
+    _want(m, "m", (n,))
+    for name, t in (("x", x), ("v", v), ("a", a)):
+        _want(t, name, (n, 3), m.device)
+    if x_hist is not None:
+        _want(x_hist, "x_hist", (steps, n, 3), m.device)
+    with _on(m.device):
+        _check(lib().nbody_leapfrog(_ptr(x), _ptr(v), _ptr(a), _ptr(m), n, _eps2(eps2), float(dt),
+                                    steps, _ptr(x_hist), _stream(m.device)))
+    return x, v, a
+
+
+def leapfrog_adjoint_(pos, m, eps2: float, dt: float, lx, lv, lm, *, flags: int = 0):
+    """In place: the reverse sweep over the ``pos.shape[0] - 1`` steps whose
+    positions ``pos`` holds (nbody_leapfrog_adjoint): (lx, lv) from the
+    segment's end to its start, dL/dm added to lm.  ``flags``: LEAPFROG_FINAL
+    and/or LEAPFROG_INITIAL."""
+    n = int(m.shape[0]) if m.dim() == 1 else -1
+    _want(m, "m", (n,))
+    steps = int(pos.shape[0]) - 1 if pos.dim() == 3 else -1
+    if steps < 0:
+        raise ValueError(f"pos must have shape [steps + 1, n, 3], got {tuple(pos.shape)}")
+    _want(pos, "pos", (steps + 1, n, 3), m.device)
+    _want(lx, "lx", (n, 3), m.device)
+    _want(lv, "lv", (n, 3), m.device)
+    _want(lm, "lm", (n,), m.device)
+    with _on(m.device):
+        _check(lib().nbody_leapfrog_adjoint(_ptr(pos), _ptr(m), n, _eps2(eps2), float(dt), steps,
+                                            int(flags), _ptr(lx), _ptr(lv), _ptr(lm),
+                                            _stream(m.device)))
+    return lx, lv, lm
+
+
 # ---------------------------------------------------------------- autograd
 
 class NBodyForces(torch.autograd.Function):
@@ -314,4 +366,10 @@ def profile_read():
     return a.value, b.value, c.value
 
 
-from .leapfrog import leapfrog  # noqa: E402  (re-export)
+def __getattr__(name):
+    # ``leapfrog`` is re-exported lazily: leapfrog.py imports this module, so
+    # either may be imported first.
+    if name == "leapfrog":
+        from .leapfrog import leapfrog
+        return leapfrog
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.nbody_abi_version() == 2
+    assert L.nbody_abi_version() == 3
     for code, name in enumerate(["NBODY_OK", "NBODY_ERROR_INVALID_ARGUMENT",
                                  "NBODY_ERROR_UNSUPPORTED_DEVICE", "NBODY_ERROR_OUT_OF_MEMORY",
                                  "NBODY_ERROR_LAUNCH_FAILED", "NBODY_ERROR_INTERNAL"]):
@@ -150,3 +150,38 @@ def test_kick_drift_validation(L):
     assert L.nbody_kick_drift(FAKE, ctypes.c_void_p(0x10004), ctypes.c_void_p(0xA0000), 4,
                               0.1, 0.1, None) == 1
     assert L.nbody_kick_drift(None, None, None, 0, 0.1, 0.1, None) == 0
+
+
+def test_leapfrog_validation(L):
+    L.nbody_leapfrog.argtypes = [vp, vp, vp, vp, i64, f32, f32, i64, vp, vp]
+    X, V, A, M = (ctypes.c_void_p(0x100000 * k) for k in (1, 2, 3, 4))
+    ok = lambda *a: L.nbody_leapfrog(*a, None)
+    assert ok(X, V, A, M, -1, 1e-4, 1e-3, 1, None) == 1                 # n < 0
+    assert ok(X, V, A, M, 4, -1.0, 1e-3, 1, None) == 1                  # eps2 < 0
+    assert ok(X, V, A, M, 4, 1e-4, float("nan"), 1, None) == 1          # dt not finite
+    assert ok(X, V, A, M, 4, 1e-4, 1e-3, -1, None) == 1                 # steps < 0
+    assert ok(X, V, A, M, 4, 1e-4, 1e-3, (1 << 30) + 1, None) == 1      # steps too large
+    assert ok(X, None, A, M, 4, 1e-4, 1e-3, 1, None) == 1               # NULL v
+    assert ok(X, ctypes.c_void_p(0x100000 + 24), A, M, 4, 1e-4, 1e-3, 1, None) == 1  # x, v overlap
+    # x_hist of 3 steps x 48 B reaches into a
+    assert ok(X, V, A, M, 4, 1e-4, 1e-3, 3, ctypes.c_void_p(0x300000 - 100)) == 1
+    assert ok(None, None, None, None, 0, 1e-4, 1e-3, 5, None) == 0      # n == 0
+    assert ok(X, V, A, M, 4, 1e-4, 1e-3, 0, None) == 0                  # no steps
+
+
+def test_leapfrog_adjoint_validation(L):
+    L.nbody_leapfrog_adjoint.argtypes = [vp, vp, i64, f32, f32, i64, ctypes.c_uint32, vp, vp,
+                                         vp, vp]
+    P, M, LX, LV, LM = (ctypes.c_void_p(0x100000 * k) for k in (1, 2, 3, 4, 5))
+    ok = lambda *a: L.nbody_leapfrog_adjoint(*a, None)
+    assert ok(P, M, 4, 1e-4, 1e-3, 2, 4, LX, LV, LM) == 1               # unknown flag bit
+    assert ok(P, M, -1, 1e-4, 1e-3, 2, 0, LX, LV, LM) == 1
+    assert ok(P, M, 4, float("inf"), 1e-3, 2, 0, LX, LV, LM) == 1
+    assert ok(P, M, 4, 1e-4, float("inf"), 2, 0, LX, LV, LM) == 1
+    assert ok(P, M, 4, 1e-4, 1e-3, -2, 0, LX, LV, LM) == 1
+    assert ok(P, M, 4, 1e-4, 1e-3, 2, 3, LX, None, LM) == 1             # NULL lv
+    assert ok(P, M, 4, 1e-4, 1e-3, 2, 0, LX, LX, LM) == 1               # lx is lv
+    # pos holds 3 x 48 B: with 0x100000 - 64 it runs into m
+    assert ok(ctypes.c_void_p(0x200000 - 64), M, 4, 1e-4, 1e-3, 2, 0, LX, LV, LM) == 1
+    assert ok(None, None, 0, 1e-4, 1e-3, 2, 3, None, None, None) == 0   # n == 0
+    assert ok(P, M, 4, 1e-4, 1e-3, 0, 3, LX, LV, LM) == 0               # no steps

@@ -156,3 +156,101 @@ def test_graph_replay_equals_eager(nb, n, steps, k):
     for got in res[1:]:
         for a, b in zip(res[0], got):
             assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# The device-resident calls (nbody_leapfrog, nbody_leapfrog_adjoint) against
+# the same updates issued one library call at a time: bitwise, whether the
+# updates run in the force kernels' reduction epilogue (pair-once variants)
+# or in a separate element-wise launch (the other variants).
+
+def _composed_forward(nb, x, v, a, m, eps2, dt, steps):
+    hist = []
+    for _ in range(steps):
+        nb.kick_drift_(x, v, a, -0.5 * dt, dt)
+        hist.append(x.clone())
+        nb.forces(x, m, eps2, out=(a, None), potential=False)
+        nb.axpy_(v, a, -0.5 * dt)
+    return hist
+
+
+def _composed_adjoint(nb, pos, m, eps2, dt, lx, lv, lm, flags):
+    steps = pos.shape[0] - 1
+    gx, gm = torch.empty_like(lx), torch.empty_like(lm)
+    half = 0.5 * dt
+    if flags & nb.LEAPFROG_FINAL:
+        nb.forces_backward(pos[steps], m, eps2, lv, None, out=(gx, gm))
+        nb.axpy_(lx, gx, -half)
+        nb.axpy_(lm, gm, -half)
+    for t in range(steps, 0, -1):
+        nb.axpy_(lv, lx, dt)
+        c = -half if (flags & nb.LEAPFROG_INITIAL and t == 1) else -dt
+        nb.forces_backward(pos[t - 1], m, eps2, lv, None, out=(gx, gm))
+        nb.axpy_(lx, gx, c)
+        nb.axpy_(lm, gm, c)
+
+
+def _forced(nb, kind, name):
+    names = nb.variant_names(kind)
+    nb.set_variant(kind, names.index(name) if name else -1)
+
+
+@pytest.mark.parametrize("n,variant", [
+    (1, None), (700, None), (4099, None), (6001, None), (20000, None), (70001, None),
+    (6001, "fwd_la_w16"), (6001, "fwd_b256_k1_u8"), (9000, "fwd_b64_k1_u8_f64sum"),
+    (9000, "fwd_sym_w8_k4_o1"), (3000, "fwd_sym_w4_k4_o1")])
+def test_leapfrog_call_equals_composed_calls(nb, n, variant):
+    dev = need_gpu()
+    x, v, m, _ = _case(n, 7)
+    xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
+    eps2, dt, steps = 1e-4, 1e-3, 5
+    print(f"[leapfrog call] n={n} variant={variant}", flush=True)
+    _forced(nb, nb.FORWARD, variant)
+    try:
+        a0, _ = nb.forces(xt, mt, eps2, potential=False)
+        x1, v1, a1 = xt.clone(), vt.clone(), a0.clone()
+        hist = torch.full((steps, n, 3), float("nan"), device=dev)
+        nb.leapfrog_(x1, v1, a1, mt, eps2, dt, steps, x_hist=hist)
+        x3, v3, a3 = xt.clone(), vt.clone(), a0.clone()
+        nb.leapfrog_(x3, v3, a3, mt, eps2, dt, steps)
+        x2, v2, a2 = xt.clone(), vt.clone(), a0.clone()
+        ref = _composed_forward(nb, x2, v2, a2, mt, eps2, dt, steps)
+        torch.cuda.synchronize()
+    finally:
+        _forced(nb, nb.FORWARD, None)
+    for got in ((x1, v1, a1), (x3, v3, a3)):
+        assert all(torch.equal(p, q) for p, q in zip(got, (x2, v2, a2)))
+    for t in range(steps):
+        assert torch.equal(hist[t], ref[t]), t
+    assert not torch.equal(x2, xt)
+
+
+@pytest.mark.parametrize("n,variant,flags", [
+    (1, None, 3), (1500, None, 3), (5000, None, 0), (5000, None, 1), (9000, None, 2),
+    (70001, None, 1), (9000, "bwd_b128_k1_u8", 3), (3000, "bwd_sym_w8_k2_o1", 1),
+    (3000, "bwd_b256_k1_u8", 0)])
+def test_leapfrog_adjoint_call_equals_composed_calls(nb, n, variant, flags):
+    dev = need_gpu()
+    x, v, m, u = _case(n, 8)
+    xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
+    eps2, dt, steps = 1e-4, 1e-3, 4
+    print(f"[leapfrog adjoint call] n={n} variant={variant} flags={flags}", flush=True)
+    a0, _ = nb.forces(xt, mt, eps2, potential=False)
+    pos = torch.empty((steps + 1, n, 3), device=dev)
+    pos[0].copy_(xt)
+    nb.leapfrog_(xt.clone(), vt.clone(), a0, mt, eps2, dt, steps, x_hist=pos[1:])
+    lx0 = to_dev(u, dev)
+    lv0 = to_dev(inputs.normal((n, 3), (70, 8, 4)), dev)
+    lm0 = to_dev(inputs.normal((n,), (70, 8, 5)), dev)
+    _forced(nb, nb.BACKWARD, variant)
+    try:
+        got = [t.clone() for t in (lx0, lv0, lm0)]
+        nb.leapfrog_adjoint_(pos, mt, eps2, dt, *got, flags=flags)
+        ref = [t.clone() for t in (lx0, lv0, lm0)]
+        _composed_adjoint(nb, pos, mt, eps2, dt, *ref, flags)
+        torch.cuda.synchronize()
+    finally:
+        _forced(nb, nb.BACKWARD, None)
+    for g, r in zip(got, ref):
+        assert torch.equal(g, r)
+    assert not torch.equal(got[1], lv0)
