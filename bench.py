@@ -15,10 +15,13 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
+import re
 import sys
+import threading
 import time
 
 import numpy as np
@@ -60,6 +63,65 @@ def read_traffic(variant: str):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _sclk_path(torch, dev):
+    """sysfs file with the driver's current graphics clock for `dev`."""
+    try:
+        pr = torch.cuda.get_device_properties(dev)
+        path = (f"/sys/bus/pci/devices/{pr.pci_domain_id:04x}:{pr.pci_bus_id:02x}:"
+                f"{pr.pci_device_id:02x}.0/pp_dpm_sclk")
+        if os.path.exists(path):
+            return path
+    except (AttributeError, RuntimeError):
+        pass
+    cands = glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")
+    return cands[0] if len(cands) == 1 else None
+
+
+class SclkSampler:
+    """Samples the graphics clock the driver reports (the line of
+    pp_dpm_sclk marked '*') every 10 ms on a host thread while the block
+    runs; ``mean_mhz`` is their mean (None where the file is unreadable)."""
+
+    def __init__(self, torch, dev):
+        self.path = _sclk_path(torch, dev)
+        self.samples = []
+        self._stop = threading.Event()
+        self._thread = None
+
+    def _read(self):
+        try:
+            with open(self.path) as f:
+                for line in f:
+                    if "*" in line:
+                        mhz = re.search(r"(\d+)\s*Mhz", line, re.I)
+                        return int(mhz.group(1)) if mhz else None
+        except OSError:
+            return None
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._read()
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(0.01)
+
+    def __enter__(self):
+        if self.path:
+            self._thread = threading.Thread(target=self._run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread:
+            self._stop.set()
+            self._thread.join()
+
+    @property
+    def mean_mhz(self):
+        return sum(self.samples) / len(self.samples) if self.samples else None
 
 
 def timed_calls(fn, reps: int, torch, nb):
@@ -240,7 +302,8 @@ def main() -> int:
         fwd()
     torch.cuda.synchronize()
     log(f"forward timed x{args.steps}")
-    wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb)
+    with SclkSampler(torch, dev) as clk:
+        wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb)
     pairs = metrics.pairs(w.n)
     ms_step = wall * 1e3 / args.steps
     value = pairs / (wall / args.steps)
@@ -269,7 +332,11 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": variant, "kernel_ms": kern_ms, "call_kernels_ms": call_ms,
-                     "flop_per_pair": metrics.FLOP_PER_PAIR},
+                     "flop_per_pair": metrics.FLOP_PER_PAIR,
+                     # the peak scaled to the clock the driver reported while timing
+                     "sclk_mhz_observed": clk.mean_mhz,
+                     "frac_at_observed_sclk": (achieved / (peak * clk.mean_mhz / 2400.0)
+                                               if clk.mean_mhz else None)},
     }
 
     # ---------------------------------------------------------- other sizes
