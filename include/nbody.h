@@ -91,15 +91,16 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 5,000 <= n <= 2^21 the default variant evaluates each
+ * Kernels: for 3,000 <= n <= 2^21 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair); it needs about 8 n^2 / P bytes of
  * library workspace, with blocks of P = 2048 particles from 2^17 up
- * (4.3 GB at n = 2^20, 17 GB at 2^21) and P = 1024 or 256 below.  Outside that range the default
- * gathers every ordered pair per row with j-splits: below 5,000 in one launch
- * whose last workgroup per 64 rows adds the splits (16 n * splits bytes of
- * workspace and one int counter per 64 rows), above 2^21 with float64 row
- * sums (as NBODY_FORCES_F64_SUM below) and a reduction launch (at most
+ * (4.3 GB at n = 2^20, 17 GB at 2^21), P = 1024 from 2^16, 256 from 12,000
+ * and 128 below.  Outside that range the default gathers every ordered
+ * pair per row with j-splits: below 3,000 in one launch whose last
+ * workgroup per 64 rows adds the splits (16 n * splits bytes of workspace
+ * and one int counter per 64 rows), above 2^21 with float64 row sums (as
+ * NBODY_FORCES_F64_SUM below) and a reduction launch (at most
  * 32 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
@@ -127,8 +128,8 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
  * float32 once at the store.  Float32 running sums add n / tile tile sums in
  * float32, an error that grows with n; the paper computes in single
  * precision throughout (Sec. IV).  The default already sums in float64
- * outside 5,000 <= n <= 2^21; inside that range the flag trades the
- * pair-once kernel for the row gather (about 20% slower at n = 2^20) and
+ * above 2^21; up to 2^21 the flag trades the pair-once (or one-launch)
+ * kernel for the row gather (about 20% slower at n = 2^20) and
  * 32 n * splits bytes of workspace.  A forced variant (nbody_set_variant)
  * is honoured only if it is one of the "_f64sum" variants.
  * Errors: as nbody_forces; unknown flag bits -> INVALID_ARGUMENT.
@@ -150,10 +151,12 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
  * Kernels: for 2^11 <= n <= 2^20 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair)
- * with about 8 n^2 / P bytes of workspace for blocks of P = 256 (below
- * 2^16) or 1024 particles (8.6 GB at n = 2^20); with grad_p NULL it does
- * not form the potential-weight terms (same result as zero weights).
- * Otherwise every ordered pair is gathered per row.
+ * with about 8 n^2 / P bytes of workspace for blocks of P = 1024
+ * particles from 2^16 (8.6 GB at n = 2^20; from 2^17 without grad_p) and
+ * of 128 or 256 below; with
+ * grad_p NULL it does not form the potential-weight terms (with the same
+ * variant, bitwise the result of zero weights) and the default may take
+ * other block shapes.  Otherwise every ordered pair is gathered per row.
  */
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
                                    const float *grad_a, const float *grad_p,
@@ -290,7 +293,11 @@ nbody_status nbody_set_variant(int kind, int index);
  */
 nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void *stream);
 
-/* Variant index the library would use for `kind` at size n (-1 on error). */
+/*
+ * Variant index the library would use for `kind` at size n (-1 on error);
+ * for NBODY_KIND_BACKWARD the choice for a call with grad_p given (without
+ * it, and in nbody_leapfrog_adjoint, the default can differ).
+ */
 int nbody_selected_variant(int kind, int64_t n);
 
 /* Free every cached workspace of every device and stream (synchronises). */

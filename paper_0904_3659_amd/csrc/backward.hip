@@ -672,6 +672,9 @@ const Variant kVariants[] = {
     BWD_SYM_VARIANT(4, 1, 1),
     BWD_SYM_VARIANT(2, 2, 1),
     BWD_SYM_VARIANT(2, 4, 1),
+    BWD_SYM_VARIANT(1, 2, 1),
+    BWD_SYM_VARIANT(2, 1, 1),
+    BWD_SYM_VARIANT(1, 4, 1),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -691,19 +694,25 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once adjoint wins from 2^13 particles on; its
-// partial buffer grows as 8 n^2 / 1024 bytes, so above 2^20 particles the
-// gather kernel takes over.
-int backward_default_variant(int64_t n)
+// Measured on MI355X: the pair-once adjoint wins from 2^11 particles on; its
+// partial buffer grows as 8 n^2 / P bytes (P = 128 to 1024), so above 2^20
+// particles the gather kernel takes over.  Without potential weights
+// (grad_p NULL) each pair costs fewer registers and one-wave blocks of 128
+// particles lead from about 6,000 to 2^17 particles (5-12% ahead of the
+// two- and eight-wave blocks at 16,384 to 65,536); with them two-wave
+// blocks lead.
+int backward_default_variant(int64_t n, bool has_v)
 {
     static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
     static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
-    static const int pair_once_small = variant_index("bwd_sym_w4_k1_o1");
+    static const int pair_once_nov = variant_index("bwd_sym_w1_k2_o1");
+    static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
     if (n > (1 << 20)) return gather;
+    if (!has_v && n >= 6000 && n < (1 << 17)) return pair_once_nov;
     if (n >= (1 << 16)) return pair_once;
-    if (n >= (1 << 13)) return pair_once_mid;
+    if (has_v && n >= 14000) return pair_once_mid;
     if (n >= (1 << 11)) return pair_once_small;
     return gather_small;
 }

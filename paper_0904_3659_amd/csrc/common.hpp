@@ -87,7 +87,8 @@ nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Devi
 // ---- backward (vector-Jacobian product of Eq. (gravity))
 int backward_variant_count();
 const char *backward_variant_name(int index);
-int backward_default_variant(int64_t n);
+// has_v: upstream potential weights (grad_p) are given.
+int backward_default_variant(int64_t n, bool has_v);
 // `epi` / `fused` as for forward_run (kLfAdjoint updates; gx, gm still
 // receive the result when the update is not fused).
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m,

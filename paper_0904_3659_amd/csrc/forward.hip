@@ -373,6 +373,9 @@ const Variant kVariants[] = {
     FWD_SYM_VARIANT(16, 4, 1),
     FWD_SYM_VARIANT(2, 4, 1),
     FWD_SYM_VARIANT(1, 4, 1),
+    FWD_SYM_VARIANT(1, 2, 1),
+    FWD_SYM_VARIANT(2, 2, 1),
+    FWD_SYM_VARIANT(4, 2, 1),
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
@@ -399,8 +402,8 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once kernel wins from about 5,000 particles
-// on; its partial buffer grows as 8 n^2 / P bytes (P = 256 to 2048
+// Measured on MI355X: the pair-once kernel wins from about 3,000 particles
+// on; its partial buffer grows as 8 n^2 / P bytes (P = 128 to 2048
 // particles per block), so beyond 2^21 particles the gather kernel, which
 // needs no workspace at that size, takes over.
 int forward_default_variant(int64_t n)
@@ -412,13 +415,18 @@ int forward_default_variant(int64_t n)
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_o1");
     static const int pair_once_1 = variant_index("fwd_sym_w1_k4_o1");
+    static const int pair_once_small = variant_index("fwd_sym_w1_k2_o1");
     if (n > (1 << 21)) return gather_big;
     // 8-wave blocks of 2,048 particles, two workgroups per CU: 1% ahead of
     // 16-wave blocks at 2^20 (same-box A/B, repeated); their partial
     // workspace is 8 n^2 / 2048 bytes (4.3 GB at 2^20, 17 GB at 2^21)
     if (n >= (1 << 17)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
-    if (n >= 5000) return pair_once_1;
+    if (n >= 12000) return pair_once_1;
+    // one-wave blocks of 128 particles: twice the workgroups of 256-particle
+    // blocks, which evens out the one round of workgroups these sizes fill
+    // (3-17% faster from 3,000 to 10,000 bodies, slower from about 12,000)
+    if (n >= 3000) return pair_once_small;
     // Small n is set by launch latency: one launch, no reduction kernel.
     return one_launch;
 }

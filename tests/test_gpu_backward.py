@@ -157,7 +157,21 @@ def test_no_potential_weights_kernel(nb, n):
     x = to_dev(inputs.plummer_positions(n, (66, n)), dev)
     m = to_dev(inputs.lognormal_masses(n, (66, n, 1)), dev)
     ga = to_dev(inputs.normal((n, 3), (66, n, 2)), dev)
-    assert nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, n)].startswith("bwd_sym")
-    gx0, gm0 = nb.forces_backward(x, m, 1e-4, ga, torch.zeros((n,), device=dev))
+    names = nb.variant_names(nb.BACKWARD)
+    v = nb.selected_variant(nb.BACKWARD, n)
+    assert names[v].startswith("bwd_sym")
+    zero = torch.zeros((n,), device=dev)
+    # the default without weights may take another block shape: equal up
+    # to float32 summation order
+    gx0, gm0 = nb.forces_backward(x, m, 1e-4, ga, zero)
     gx1, gm1 = nb.forces_backward(x, m, 1e-4, ga, None)
-    assert torch.equal(gx0, gx1) and torch.equal(gm0, gm1)
+    for g0, g1 in ((gx0, gx1), (gm0, gm1)):
+        e = ((g0 - g1).abs().max() / g0.abs().max()).item()
+        assert e <= 1e-5, e
+    # the same variant with and without the weight terms: bitwise
+    nb.set_variant(nb.BACKWARD, v)
+    try:
+        gx2, gm2 = nb.forces_backward(x, m, 1e-4, ga, None)
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+    assert torch.equal(gx0, gx2) and torch.equal(gm0, gm2)
