@@ -283,10 +283,10 @@ def leapfrog_adjoint_(pos, m, eps2: float, dt: float, lx, lv, lm, *, flags: int 
     segment's end to its start, dL/dm added to lm.  ``flags``: LEAPFROG_FINAL
     and/or LEAPFROG_INITIAL."""
     n = int(m.shape[0]) if m.dim() == 1 else -1
-    _want(m, "m", (n,))
     steps = int(pos.shape[0]) - 1 if pos.dim() == 3 else -1
     if steps < 0:
         raise ValueError(f"pos must have shape [steps + 1, n, 3], got {tuple(pos.shape)}")
+    _want(m, "m", (n,))
     _want(pos, "pos", (steps + 1, n, 3), m.device)
     _want(lx, "lx", (n, 3), m.device)
     _want(lv, "lv", (n, 3), m.device)
