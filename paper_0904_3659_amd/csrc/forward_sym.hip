@@ -87,7 +87,6 @@ nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Devi
     if (W == 4 && K == 8 && occ == 1) return run_sym<4, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     if (W == 4 && K == 4 && occ == 1) return run_sym<4, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     if (W == 2 && K == 8 && occ == 1) return run_sym<2, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
-    if (W == 1 && K == 8 && occ == 1) return run_sym<1, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     if (W == 16 && K == 4 && occ == 1) return run_sym<16, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     if (W == 2 && K == 4 && occ == 1) return run_sym<2, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
     if (W == 1 && K == 4 && occ == 1) return run_sym<1, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused);
