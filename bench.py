@@ -124,6 +124,18 @@ class SclkSampler:
         return sum(self.samples) / len(self.samples) if self.samples else None
 
 
+def warm_up(fn, torch, seconds: float = 0.1, min_calls: int = 3) -> None:
+    """Call fn() (synchronising after each call) for at least `seconds` of
+    wall time and `min_calls` calls, so that the GPU clock has come back up
+    after host-side work before a timed loop."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < min_calls or time.perf_counter() - t0 < seconds:
+        fn()
+        torch.cuda.synchronize()
+        k += 1
+
+
 def timed_calls(fn, reps: int, torch, nb):
     """Run fn() reps times between two synchronisations.
 
@@ -236,7 +248,7 @@ def size_sweep(nb, torch, dev, inputs, metrics):
         for label, vname in SWEEP_PROGRAMS:
             nb.set_variant(nb.FORWARD, names.index(vname) if vname else -1)
             f = lambda: nb.forces(x, m, 1e-4)
-            f()
+            warm_up(f, torch, 0.05, 1)
             wall, _, _ = timed_calls(f, reps, torch, nb)
             row[label] = {"variant": vname or names[nb.selected_variant(nb.FORWARD, n)],
                           "ms": wall * 1e3 / reps,
@@ -346,8 +358,7 @@ def main() -> int:
             ws = make()
             xs, ms_ = torch.from_numpy(ws.x).to(dev), torch.from_numpy(ws.m).to(dev)
             f = lambda: nb.forces(xs, ms_, ws.eps2)
-            for _ in range(3):
-                f()
+            warm_up(f, torch)
             reps = 50 if ws.n <= 4096 else 20
             wl, km, cm = timed_calls(f, reps, torch, nb)
             pr = metrics.pairs(ws.n)
@@ -369,8 +380,7 @@ def main() -> int:
         gx = torch.empty_like(xa)
         gm = torch.empty_like(ma)
         bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
-        for _ in range(3):
-            bwd()
+        warm_up(bwd, torch)
         wall_a, ka, ca = timed_calls(bwd, 50, torch, nb)
         pa = metrics.pairs(wa.n)
         out["adjoint"] = {
@@ -427,8 +437,7 @@ def main() -> int:
         torch.cuda.synchronize()
         plan_s = time.perf_counter() - t0
         bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
-        for _ in range(2):
-            bat()
+        warm_up(bat, torch)
         wall_b, kbm, kb = timed_calls(bat, 10, torch, nb)
         views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
                  for lo, hi in zip(ens.offsets[:-1], ens.offsets[1:]) if hi > lo]
@@ -472,7 +481,7 @@ def main() -> int:
                              ("default", None)):
             nb.set_variant(nb.FORWARD, names.index(vname) if vname else -1)
             f = lambda: nb.forces(xu, mu, wu[4])
-            f()
+            warm_up(f, torch, 0.1, 1)
             wl, km, cm = timed_calls(f, 10, torch, nb)
             pr = metrics.pairs(xu.shape[0]) / (wl / 10)
             study[label] = {"variant": vname or names[nb.selected_variant(nb.FORWARD, xu.shape[0])],
