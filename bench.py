@@ -186,8 +186,15 @@ def cpu_baseline(w, budget_s: float = 12.0):
             done1 += part.size
     finally:
         R.set_num_threads(threads)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
     return {"value": pairs / spent, "unit": "pair-interactions/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{done} seeded rows x {n - 1} j of {w.name}, FP64, {spent:.2f} s",
             "single_thread_value": done1 * (n - 1) / spent1,
             "single_thread_sample": f"first {done1} of the same rows, 1 thread, {spent1:.2f} s"}
