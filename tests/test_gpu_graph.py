@@ -1,7 +1,8 @@
 """Library calls captured in a HIP graph (torch.cuda.CUDAGraph) and replayed:
 every replay must reproduce the eager result bitwise, with eager work between
 the replays, for each kernel family (one-launch, split-gather, pair-once
-forward; pair-once adjoint; persistent batched with its ticket counters)."""
+forward; pair-once adjoint; persistent batched with its ticket counters; the
+device-resident leap-frog segments and their reverse sweep)."""
 
 import numpy as np
 import pytest
@@ -79,3 +80,45 @@ def test_batched_graph(nb):
     p = torch.empty_like(m)
     _replay_matches(lambda: nb.forces_batched(x, m, ens.offsets, ens.eps2, out=(a, p)), [a, p],
                     lambda: nb.forces(x[:300], m[:300], 1e-4))
+
+
+@pytest.mark.parametrize("n", [1500, 20000])
+def test_leapfrog_graphs(nb, n):
+    # whole leap-frog segments captured as one graph: the forward steps with
+    # their position history, and the reverse sweep; n = 1500 runs the
+    # one-launch force and gather adjoint (element-wise update launches,
+    # the adjoint's auxiliary buffer), n = 20000 the pair-once kernels with
+    # the updates in their reduction epilogue
+    dev = need_gpu()
+    x0 = to_dev(inputs.plummer_positions(n, (75, n)), dev)
+    v0 = to_dev(inputs.plummer_velocities(inputs.plummer_positions(n, (75, n)), (75, n, 1)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (75, n, 2)), dev)
+    a0, _ = nb.forces(x0, m, 1e-4, potential=False)
+    steps = 6
+    x, v, a = torch.empty_like(x0), torch.empty_like(v0), torch.empty_like(a0)
+    hist = torch.empty((steps, n, 3), device=dev)
+
+    def fwd():
+        x.copy_(x0)
+        v.copy_(v0)
+        a.copy_(a0)
+        nb.leapfrog_(x, v, a, m, 1e-4, 1e-3, steps, x_hist=hist)
+
+    xo, mo = x0[: n // 2], m[: n // 2]
+    _replay_matches(fwd, [x, v, a, hist], lambda: nb.forces(xo, mo, 1e-4))
+
+    pos = torch.cat([x0[None], hist], dim=0).contiguous()
+    lx0 = to_dev(inputs.normal((n, 3), (75, n, 3)), dev)
+    lv0 = to_dev(inputs.normal((n, 3), (75, n, 4)), dev)
+    lm0 = torch.zeros((n,), device=dev)
+    lx, lv, lm = torch.empty_like(lx0), torch.empty_like(lv0), torch.empty_like(lm0)
+
+    def rev():
+        lx.copy_(lx0)
+        lv.copy_(lv0)
+        lm.copy_(lm0)
+        nb.leapfrog_adjoint_(pos, m, 1e-4, 1e-3, lx, lv, lm,
+                             flags=nb.LEAPFROG_FINAL | nb.LEAPFROG_INITIAL)
+
+    _replay_matches(rev, [lx, lv, lm],
+                    lambda: nb.forces_backward(xo, mo, 1e-4, lx0[: n // 2], None))
