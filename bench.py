@@ -2,14 +2,18 @@
 
 One step is one evaluation of Eq. (gravity) (a_i and p_i for every i, j != i)
 on a 2^20-particle Plummer sphere with log-normal masses and eps^2 = 1e-6,
-inputs resident in HBM.  The JSON line also reports the adjoint
-(nbody_forces_backward on a 16,384-particle Plummer sphere) and the batched
-ensemble (4,096 Plummer systems of 8..2048 particles in one persistent
-launch, against one plain launch per system), the roofline position of the
-forward kernel, and the FP64 CPU reference timed on a bounded sample of the
-same workload on this host's cores.
+inputs resident in HBM.  The JSON line also reports the forward at 1,024
+and 65,536 bodies, the adjoint (nbody_forces_backward on a 16,384-particle
+Plummer sphere), the gradient of a 64-step checkpointed leap-frog run, the
+batched ensemble (4,096 Plummer systems of 8..2048 particles in one
+persistent launch, against one plain launch per system), the paper's three
+unrolling programs at 100,000 bodies, 100-step stand-ins for the runs of
+Sec. V-A, the roofline position of the forward kernel, and the FP64 CPU
+reference timed on a bounded sample of the same workload on this host's
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --size-sweep     (pairs/s against N instead of the legs)
 """
 
 from __future__ import annotations
