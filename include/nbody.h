@@ -294,6 +294,20 @@ nbody_status nbody_set_variant(int kind, int index);
 nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void *stream);
 
 /*
+ * The variant timer on the caller's own ensemble: time every batched
+ * variant on (offsets, x, m, eps2) exactly as nbody_forces_batched would
+ * run it (results go to library-allocated scratch arrays, freed before
+ * returning) and record the fastest for the bucket of the mean system size
+ * offsets[num_systems] / num_systems, as nbody_autotune does.  Blocks the
+ * host until the timing runs finish; builds and caches the plans.
+ * Errors: the offsets, eps2, pointer and overlap rules of
+ * nbody_forces_batched -> INVALID_ARGUMENT; OUT_OF_MEMORY if the scratch
+ * arrays cannot be allocated.
+ */
+nbody_status nbody_autotune_batched(const int64_t *offsets, int64_t num_systems, const float *x,
+                                    const float *m, float eps2, void *stream);
+
+/*
  * Variant index the library would use for `kind` at size n (-1 on error);
  * for NBODY_KIND_BACKWARD the choice for a call with grad_p given (without
  * it, and in nbody_leapfrog_adjoint, the default can differ).

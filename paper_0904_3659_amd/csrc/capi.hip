@@ -486,10 +486,8 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
     return st;
 }
 
-nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, const float *x,
-                                  const float *m, float eps2, float *a, float *p, void *stream)
+static nbody_status check_offsets(const int64_t *offsets, int64_t num_systems)
 {
-    clear_error();
     if (num_systems < 0) return fail(NBODY_ERROR_INVALID_ARGUMENT, "num_systems = %lld < 0", (long long)num_systems);
     if (!offsets) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL offsets");
     if (offsets[0] != 0) return fail(NBODY_ERROR_INVALID_ARGUMENT, "offsets[0] = %lld, must be 0", (long long)offsets[0]);
@@ -500,6 +498,15 @@ nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, c
         if (ns > NBODY_MAX_N || offsets[s + 1] > NBODY_MAX_N)
             return fail(NBODY_ERROR_INVALID_ARGUMENT, "system %lld exceeds NBODY_MAX_N", (long long)s);
     }
+    return NBODY_OK;
+}
+
+nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, const float *x,
+                                  const float *m, float eps2, float *a, float *p, void *stream)
+{
+    clear_error();
+    nbody_status ost = check_offsets(offsets, num_systems);
+    if (ost != NBODY_OK) return ost;
     if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
     const int64_t n = offsets[num_systems];
     if (n == 0) return NBODY_OK;
@@ -778,6 +785,24 @@ nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void 
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     return autotune_run(kind, dev, sizes, count, (hipStream_t)stream);
+}
+
+nbody_status nbody_autotune_batched(const int64_t *offsets, int64_t num_systems, const float *x,
+                                    const float *m, float eps2, void *stream)
+{
+    clear_error();
+    nbody_status st = check_offsets(offsets, num_systems);
+    if (st != NBODY_OK) return st;
+    if (bad_eps2(eps2)) return fail(NBODY_ERROR_INVALID_ARGUMENT, "eps2 = %g is negative or not finite", eps2);
+    const int64_t n = offsets[num_systems];
+    if (n == 0) return NBODY_OK;
+    if (!x || !m) return fail(NBODY_ERROR_INVALID_ARGUMENT, "NULL x or m with %lld particles", (long long)n);
+    if (overlaps(x, 12 * (size_t)n, m, 4 * (size_t)n))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT, "x and m overlap");
+    Device dev;
+    st = current_device(&dev);
+    if (st != NBODY_OK) return st;
+    return autotune_batched_run(dev, offsets, num_systems, x, m, eps2, (hipStream_t)stream);
 }
 
 }  // extern "C"

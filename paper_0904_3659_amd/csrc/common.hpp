@@ -123,6 +123,10 @@ nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint3
 // ---- variant timer (nbody_autotune)
 nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int64_t count,
                           hipStream_t stream);
+// Times every batched variant on the caller's ensemble and records the
+// fastest for the bucket of its mean system size.
+nbody_status autotune_batched_run(const Device &dev, const int64_t *offsets, int64_t num_systems,
+                                  const float *x, const float *m, float eps2, hipStream_t stream);
 
 // ---- errors
 const char *last_error_cstr();

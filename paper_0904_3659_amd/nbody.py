@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_variant_name.restype = ctypes.c_char_p
         L.nbody_set_variant.argtypes = [ctypes.c_int, ctypes.c_int]
         L.nbody_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(_i64), _i64, _vp]
+        L.nbody_autotune_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp]
         L.nbody_profile_enable.argtypes = [ctypes.c_int]
         L.nbody_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double),
@@ -81,7 +82,8 @@ def lib() -> ctypes.CDLL:
         for f in ("nbody_forces", "nbody_forces_ex", "nbody_forces_backward", "nbody_forces_batched",
                   "nbody_axpy",
                   "nbody_kick_drift", "nbody_leapfrog", "nbody_leapfrog_adjoint",
-                  "nbody_set_variant", "nbody_autotune", "nbody_release_workspace",
+                  "nbody_set_variant", "nbody_autotune", "nbody_autotune_batched",
+                  "nbody_release_workspace",
                   "nbody_profile_enable", "nbody_profile_read"):
             getattr(L, f).restype = ctypes.c_int
         if L.nbody_abi_version() != ABI_VERSION:
@@ -348,6 +350,22 @@ def autotune(kind: int, sizes, device=None) -> None:
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     with _on(dev):
         _check(lib().nbody_autotune(kind, s.ctypes.data_as(ctypes.POINTER(_i64)), s.size, _stream(dev)))
+
+
+def autotune_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float) -> int:
+    """Time every batched variant on this ensemble, keep the fastest for its
+    mean system size, and return that variant's index."""
+    o = _offsets_array(offsets)
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    _want(m, "m", (n,), x.device)
+    if int(o[-1]) != n:
+        raise ValueError(f"offsets[-1] = {int(o[-1])} but x holds {n} particles")
+    with _on(x.device):
+        _check(lib().nbody_autotune_batched(o.ctypes.data_as(ctypes.POINTER(_i64)), o.size - 1,
+                                            _ptr(x), _ptr(m), _eps2(eps2), _stream(x.device)))
+    systems = o.size - 1
+    return selected_variant(BATCHED, n // systems if systems > 0 else 0)
 
 
 def release_workspace() -> None:

@@ -185,3 +185,18 @@ def test_leapfrog_adjoint_validation(L):
     assert ok(ctypes.c_void_p(0x200000 - 64), M, 4, 1e-4, 1e-3, 2, 0, LX, LV, LM) == 1
     assert ok(None, None, 0, 1e-4, 1e-3, 2, 3, None, None, None) == 0   # n == 0
     assert ok(P, M, 4, 1e-4, 1e-3, 0, 3, LX, LV, LM) == 0               # no steps
+
+
+def test_autotune_batched_validation(L):
+    L.nbody_autotune_batched.argtypes = [ctypes.POINTER(i64), i64, vp, vp, f32, vp]
+    P = ctypes.POINTER(i64)
+    ok = lambda o, s, x, m, e: L.nbody_autotune_batched(
+        None if o is None else o.ctypes.data_as(P), s, x, m, e, None)
+    X, M = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    assert ok(None, 1, X, M, 1e-4) == 1                                   # NULL offsets
+    assert ok(np.array([1, 4], dtype=np.int64), 1, X, M, 1e-4) == 1       # offsets[0] != 0
+    assert ok(np.array([0, 4, 2], dtype=np.int64), 2, X, M, 1e-4) == 1    # decreasing
+    assert ok(np.array([0, 4], dtype=np.int64), 1, X, M, -1.0) == 1       # eps2 < 0
+    assert ok(np.array([0, 4], dtype=np.int64), 1, None, M, 1e-4) == 1    # NULL x
+    assert ok(np.array([0, 4], dtype=np.int64), 1, X, ctypes.c_void_p(0x100000 + 8), 1e-4) == 1
+    assert ok(np.array([0, 0, 0], dtype=np.int64), 2, None, None, 1e-4) == 0   # nothing to time

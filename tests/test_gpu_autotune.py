@@ -55,3 +55,40 @@ def test_autotune_writes_and_reads_cache(tmp_path):
                           text=True, timeout=300)
     assert out2.returncode == 0, out2.stderr[-2000:]
     assert json.loads(out2.stdout.strip().splitlines()[-1])["fwd"] == chosen["fwd"][0]
+
+
+CHILD_ENSEMBLE = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+from oracle import reference as R
+from paper_0904_3659_amd import inputs
+from paper_0904_3659_amd import nbody as nb
+ens = inputs.ensemble([5, 0, 300, 64, 1, 700, 129, 2048, 33], key=(93,))
+dev = torch.device("cuda", 0)
+x, m = torch.from_numpy(ens.x).to(dev), torch.from_numpy(ens.m).to(dev)
+v = nb.autotune_batched(x, m, ens.offsets, ens.eps2)
+a, p = nb.forces_batched(x, m, ens.offsets, ens.eps2)
+nb.set_variant(nb.BATCHED, v)
+a2, p2 = nb.forces_batched(x, m, ens.offsets, ens.eps2)
+nb.set_variant(nb.BATCHED, -1)
+ar, pr = R.forces_batched(ens.offsets, ens.x, ens.m, ens.eps2)
+ok = pr > 0
+err = float(np.max(np.abs(p.cpu().numpy() - pr)[ok] / pr[ok]))
+print(json.dumps({"variant": v, "same": bool(torch.equal(a, a2) and torch.equal(p, p2)),
+                  "err": err, "count": nb.variant_count(nb.BATCHED)}))
+"""
+
+
+def test_autotune_on_the_callers_ensemble(tmp_path):
+    # the ensemble tuner records a choice for the mean system size; the next
+    # batched call on that ensemble uses it, and it passes parity
+    need_gpu()
+    env = dict(os.environ, NBODY_TUNE_CACHE=str(tmp_path / "tune.json"))
+    out = subprocess.run([sys.executable, "-c", CHILD_ENSEMBLE, ROOT], env=env, cwd=ROOT,
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    assert 0 <= r["variant"] < r["count"]
+    assert r["same"]
+    assert r["err"] <= 1e-4
