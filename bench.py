@@ -141,19 +141,26 @@ def warm_up(fn, torch, seconds: float = 0.1, min_calls: int = 3) -> None:
 
 
 def timed_calls(fn, reps: int, torch, nb):
-    """Run fn() reps times between two synchronisations.
+    """Run fn() reps times between two synchronisations, then reps times
+    more with the library's kernel timing on.
 
-    Returns (wall seconds of the loop, mean pair-kernel ms, mean whole-call
-    kernel ms).  The kernel figures come from the library's own HIP events,
-    recorded on the stream it launches on (torch's current stream) around
-    its pair kernel and after its last kernel."""
+    Returns (wall seconds of the first loop, mean pair-kernel ms, mean
+    whole-call kernel ms).  The kernel figures come from the library's own
+    HIP events, recorded on the stream it launches on (torch's current
+    stream) around its pair kernel and after its last kernel; they are taken
+    in the second loop so that recording them does not slow the timed one
+    (it adds several microseconds per call at small n)."""
     torch.cuda.synchronize()
-    nb.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(reps):
         fn()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    nb.profile_enable(True)
+    nb.profile_read()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
     main_ms, total_ms, calls = nb.profile_read()
     nb.profile_enable(False)
     assert calls == reps, (calls, reps)
