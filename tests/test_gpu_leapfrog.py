@@ -195,16 +195,17 @@ def _forced(nb, kind, name):
     nb.set_variant(kind, names.index(name) if name else -1)
 
 
-@pytest.mark.parametrize("n,variant", [
-    (1, None), (700, None), (4099, None), (6001, None), (20000, None), (70001, None),
-    (6001, "fwd_la_w16"), (6001, "fwd_b256_k1_u8"), (9000, "fwd_b64_k1_u8_f64sum"),
-    (9000, "fwd_sym_w8_k4_o1"), (3000, "fwd_sym_w4_k4_o1")])
-def test_leapfrog_call_equals_composed_calls(nb, n, variant):
+@pytest.mark.parametrize("n,variant,steps", [
+    (1, None, 5), (2, None, 3), (700, None, 5), (4099, None, 5), (6001, None, 5),
+    (20000, None, 5), (70001, None, 5), (3001, None, 1), (700, None, 1),
+    (6001, "fwd_la_w16", 5), (6001, "fwd_b256_k1_u8", 5), (9000, "fwd_b64_k1_u8_f64sum", 5),
+    (9000, "fwd_sym_w8_k4_o1", 5), (3000, "fwd_sym_w4_k4_o1", 5)])
+def test_leapfrog_call_equals_composed_calls(nb, n, variant, steps):
     dev = need_gpu()
     x, v, m, _ = _case(n, 7)
     xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
-    eps2, dt, steps = 1e-4, 1e-3, 5
-    print(f"[leapfrog call] n={n} variant={variant}", flush=True)
+    eps2, dt = 1e-4, 1e-3
+    print(f"[leapfrog call] n={n} variant={variant} steps={steps}", flush=True)
     _forced(nb, nb.FORWARD, variant)
     try:
         a0, _ = nb.forces(xt, mt, eps2, potential=False)
@@ -225,16 +226,17 @@ def test_leapfrog_call_equals_composed_calls(nb, n, variant):
     assert not torch.equal(x2, xt)
 
 
-@pytest.mark.parametrize("n,variant,flags", [
-    (1, None, 3), (1500, None, 3), (5000, None, 0), (5000, None, 1), (9000, None, 2),
-    (70001, None, 1), (9000, "bwd_b128_k1_u8", 3), (3000, "bwd_sym_w8_k2_o1", 1),
-    (3000, "bwd_b256_k1_u8", 0)])
-def test_leapfrog_adjoint_call_equals_composed_calls(nb, n, variant, flags):
+@pytest.mark.parametrize("n,variant,flags,steps", [
+    (1, None, 3, 4), (2, None, 3, 2), (1500, None, 3, 4), (5000, None, 0, 4), (5000, None, 1, 4),
+    (9000, None, 2, 4), (70001, None, 1, 4), (6001, None, 3, 1), (6001, None, 0, 1),
+    (9000, "bwd_b128_k1_u8", 3, 4), (3000, "bwd_sym_w8_k2_o1", 1, 4),
+    (3000, "bwd_b256_k1_u8", 0, 4)])
+def test_leapfrog_adjoint_call_equals_composed_calls(nb, n, variant, flags, steps):
     dev = need_gpu()
     x, v, m, u = _case(n, 8)
     xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
-    eps2, dt, steps = 1e-4, 1e-3, 4
-    print(f"[leapfrog adjoint call] n={n} variant={variant} flags={flags}", flush=True)
+    eps2, dt = 1e-4, 1e-3
+    print(f"[leapfrog adjoint call] n={n} variant={variant} flags={flags} steps={steps}", flush=True)
     a0, _ = nb.forces(xt, mt, eps2, potential=False)
     pos = torch.empty((steps + 1, n, 3), device=dev)
     pos[0].copy_(xt)
