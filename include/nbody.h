@@ -29,9 +29,11 @@
  *   allocates and a first batched call synchronises, which capture forbids).
  *   The graph keeps the workspace addresses of that stream: while it may
  *   replay, make no call on that stream that needs a larger workspace, do
- *   not call nbody_release_workspace(), and keep the number of distinct
- *   batched offset sets below the plan cache size (8).  No memset is
- *   recorded: counters are cleared by the kernels that use them.
+ *   not call nbody_release_workspace(), run no variant timer
+ *   (nbody_autotune, nbody_autotune_batched) on that stream, and keep the
+ *   number of distinct (offsets, variant) pairs of batched
+ *   calls below the plan cache size (8).  No memset is recorded: counters
+ *   are cleared by the kernels that use them.
  * - No C++ exception crosses this interface.  Every call returns a status;
  *   on failure nbody_last_error() gives a thread-local detail string.
  *   Argument checks run before any HIP call, so an invalid call touches no
@@ -299,7 +301,10 @@ nbody_status nbody_autotune(int kind, const int64_t *sizes, int64_t count, void 
  * run it (results go to library-allocated scratch arrays, freed before
  * returning) and record the fastest for the bucket of the mean system size
  * offsets[num_systems] / num_systems, as nbody_autotune does.  Blocks the
- * host until the timing runs finish; builds and caches the plans.
+ * host until the timing runs finish.  The timing runs build their plans
+ * outside the plan cache and free them; only the winner's plan is then
+ * built into the cache (one ordinary run).  The runs use `stream` and may
+ * grow its workspace.
  * Errors: the offsets, eps2, pointer and overlap rules of
  * nbody_forces_batched -> INVALID_ARGUMENT; OUT_OF_MEMORY if the scratch
  * arrays cannot be allocated.

@@ -93,12 +93,16 @@ nbody_status autotune_batched_run(const Device &dev, const int64_t *offsets, int
     nbody_status st;
     if ((st = buf.alloc(12 * (size_t)n, &a)) || (st = buf.alloc(4 * (size_t)n, &p))) return st;
     int best = -1;
+    // the timing runs' plans stay out of the shared cache; the winner's is
+    // then built there by one ordinary run
+    begin_private_batched_plans();
     st = time_best(batched_variant_count(), stream, [&](int v) {
         return batched_run(v, dev, offsets, num_systems, x, m, eps2, a, p, stream);
     }, &best);
+    end_private_batched_plans();
     if (st != NBODY_OK) return st;
     record_tuned_variant(NBODY_KIND_BATCHED, num_systems > 0 ? n / num_systems : 0, best);
-    return NBODY_OK;
+    return batched_run(best, dev, offsets, num_systems, x, m, eps2, a, p, stream);
 }
 
 nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int64_t count,
@@ -120,9 +124,11 @@ nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int
                 (st = buf.alloc(12 * (size_t)n, &a)) || (st = buf.alloc(4 * (size_t)n, &p)))
                 return st;
             if ((st = fill_synthetic(x, m, nullptr, nullptr, n, 7u, stream)) != NBODY_OK) return st;
+            begin_private_batched_plans();  // plans of synthetic offsets: not kept
             st = time_best(batched_variant_count(), stream, [&](int v) {
                 return batched_run(v, dev, offsets.data(), systems, x, m, 1e-4f, a, p, stream);
             }, &best);
+            end_private_batched_plans();
             if (st != NBODY_OK) return st;
             record_tuned_variant(kind, ns, best);
             continue;

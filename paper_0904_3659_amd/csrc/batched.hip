@@ -261,20 +261,27 @@ std::mutex g_plan_mu;
 std::vector<std::shared_ptr<Plan>> g_plans;  // most recent last
 constexpr size_t kMaxPlans = 8;
 
+// While on (the variant timer), this thread's plans go to a private list
+// instead of the shared cache: timing every variant then evicts no plan
+// that a caller's captured graph may still read.
+thread_local bool t_private_on = false;
+thread_local std::vector<std::shared_ptr<Plan>> t_private_plans;
+
 nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
                         int64_t num_systems, hipStream_t stream, std::shared_ptr<Plan> *out)
 {
     const Variant &V = kVariants[variant];
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    for (size_t k = 0; k < g_plans.size(); ++k) {
-        Plan *pl = g_plans[k].get();
+    std::vector<std::shared_ptr<Plan>> &plans = t_private_on ? t_private_plans : g_plans;
+    for (size_t k = 0; k < plans.size(); ++k) {
+        Plan *pl = plans[k].get();
         if (pl->device == dev.id && pl->variant == variant &&
             pl->offsets.size() == (size_t)num_systems + 1 &&
             std::memcmp(pl->offsets.data(), offsets, sizeof(int64_t) * (num_systems + 1)) == 0) {
             // move to the back (most recently used)
-            std::shared_ptr<Plan> keep = g_plans[k];
-            g_plans.erase(g_plans.begin() + k);
-            g_plans.push_back(keep);
+            std::shared_ptr<Plan> keep = plans[k];
+            plans.erase(plans.begin() + k);
+            plans.push_back(keep);
             *out = keep;
             return NBODY_OK;
         }
@@ -347,8 +354,9 @@ nbody_status build_plan(int variant, const Device &dev, const int64_t *offsets,
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(batched plan)");
     }
-    if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());  // hipFree syncs the device
-    g_plans.push_back(plan);
+    if (!t_private_on && plans.size() >= kMaxPlans)
+        plans.erase(plans.begin());  // hipFree syncs the device
+    plans.push_back(plan);
     *out = plan;
     return NBODY_OK;
 }
@@ -384,6 +392,15 @@ void release_batched_plans()
 {
     std::lock_guard<std::mutex> lock(g_plan_mu);
     g_plans.clear();
+}
+
+void begin_private_batched_plans() { t_private_on = true; }
+
+void end_private_batched_plans()
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    t_private_on = false;
+    t_private_plans.clear();  // hipFree in each plan's destructor syncs the device
 }
 
 nbody_status batched_run(int variant, const Device &dev, const int64_t *offsets,

@@ -133,6 +133,10 @@ const char *last_error_cstr();
 
 // ---- workspace release hooks of the batched plan cache
 void release_batched_plans();
+// Until end_private_batched_plans(), batched plans built on this thread go
+// to a private list (not the shared cache); the end frees them.
+void begin_private_batched_plans();
+void end_private_batched_plans();
 
 }  // namespace nbody
 

@@ -92,3 +92,49 @@ def test_autotune_on_the_callers_ensemble(tmp_path):
     assert 0 <= r["variant"] < r["count"]
     assert r["same"]
     assert r["err"] <= 1e-4
+
+
+CHILD_GRAPH = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_0904_3659_amd import inputs
+from paper_0904_3659_amd import nbody as nb
+dev = torch.device("cuda", 0)
+ens = inputs.ensemble([300, 17, 900, 64, 2000], key=(96,))
+x, m = torch.from_numpy(ens.x).to(dev), torch.from_numpy(ens.m).to(dev)
+a, p = torch.empty_like(x), torch.empty_like(m)
+s = torch.cuda.Stream()
+s.wait_stream(torch.cuda.current_stream())
+with torch.cuda.stream(s):
+    nb.forces_batched(x, m, ens.offsets, ens.eps2, out=(a, p))
+s.synchronize()
+ref = (a.clone(), p.clone())
+g = torch.cuda.CUDAGraph()
+with torch.cuda.graph(g, stream=s):
+    nb.forces_batched(x, m, ens.offsets, ens.eps2, out=(a, p))
+torch.cuda.synchronize()
+same = []
+for r in range(3):
+    a.fill_(7.0 + r)
+    p.fill_(7.0 + r)
+    s2 = torch.cuda.Stream()
+    with torch.cuda.stream(s2):
+        nb.autotune_batched(x.clone(), m.clone(), ens.offsets, ens.eps2)
+    s2.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    same.append(bool(torch.equal(a, ref[0]) and torch.equal(p, ref[1])))
+print(json.dumps({"same": same}))
+"""
+
+
+def test_ensemble_timer_keeps_a_captured_plan():
+    # a batched graph captured first replays bitwise after each run of the
+    # ensemble variant timer on another stream: the timer's plans stay out of
+    # the shared plan cache, so none of the graph's plan is evicted
+    need_gpu()
+    out = subprocess.run([sys.executable, "-c", CHILD_GRAPH, ROOT], cwd=ROOT, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert json.loads(out.stdout.strip().splitlines()[-1])["same"] == [True, True, True]

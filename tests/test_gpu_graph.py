@@ -122,3 +122,4 @@ def test_leapfrog_graphs(nb, n):
 
     _replay_matches(rev, [lx, lv, lm],
                     lambda: nb.forces_backward(xo, mo, 1e-4, lx0[: n // 2], None))
+
