@@ -27,8 +27,9 @@
  *   has run eagerly on that stream (so that the
  *   stream's workspace, counters and the batched plan exist; a first call
  *   allocates and a first batched call synchronises, which capture forbids).
- *   The graph keeps the workspace addresses of that stream: while it may
- *   replay, make no call on that stream that needs a larger workspace, do
+ *   The graph keeps the workspace addresses of that stream (partial sums,
+ *   the leap-frog adjoint's 16 n-byte buffer, counters): while it may
+ *   replay, make no call on that stream that needs a larger one of them, do
  *   not call nbody_release_workspace(), run no variant timer
  *   (nbody_autotune, nbody_autotune_batched) on that stream, and keep the
  *   number of distinct (offsets, variant) pairs of batched
