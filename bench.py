@@ -140,27 +140,30 @@ def warm_up(fn, torch, seconds: float = 0.1, min_calls: int = 3) -> None:
         k += 1
 
 
-def timed_calls(fn, reps: int, torch, nb):
-    """Run fn() reps times between two synchronisations, then reps times
-    more with the library's kernel timing on.
+def timed_calls(fn, reps: int, torch, nb, events_in_timed_loop: bool = False):
+    """Run fn() reps times between two synchronisations.
 
-    Returns (wall seconds of the first loop, mean pair-kernel ms, mean
-    whole-call kernel ms).  The kernel figures come from the library's own
-    HIP events, recorded on the stream it launches on (torch's current
-    stream) around its pair kernel and after its last kernel; they are taken
-    in the second loop so that recording them does not slow the timed one
-    (it adds several microseconds per call at small n)."""
+    Returns (wall seconds of that loop, mean pair-kernel ms, mean whole-call
+    kernel ms).  The kernel figures come from the library's own HIP events,
+    recorded on the stream it launches on (torch's current stream) around
+    its pair kernel and after its last kernel.  With events_in_timed_loop
+    they are recorded inside the timed loop itself (the 2^20 forward, where
+    they cost nothing measurable); otherwise a second loop of reps calls
+    records them, since at small n the records add several microseconds
+    per call to the loop they sit in."""
     torch.cuda.synchronize()
+    if events_in_timed_loop:
+        nb.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(reps):
         fn()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    nb.profile_enable(True)
-    nb.profile_read()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
+    if not events_in_timed_loop:
+        nb.profile_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
     main_ms, total_ms, calls = nb.profile_read()
     nb.profile_enable(False)
     assert calls == reps, (calls, reps)
@@ -333,7 +336,7 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"forward timed x{args.steps}")
     with SclkSampler(torch, dev) as clk:
-        wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb)
+        wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb, events_in_timed_loop=True)
     pairs = metrics.pairs(w.n)
     ms_step = wall * 1e3 / args.steps
     value = pairs / (wall / args.steps)
