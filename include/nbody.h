@@ -154,12 +154,12 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
  * Kernels: for 2^11 <= n <= 2^20 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair)
- * with about 8 n^2 / P bytes of workspace for blocks of P = 1024
+ * with about 8 n^2 / P bytes of workspace, for blocks of P = 1024
  * particles from 2^16 (8.6 GB at n = 2^20; from 2^17 without grad_p) and
- * of 128 or 256 below; with
- * grad_p NULL it does not form the potential-weight terms (with the same
- * variant, bitwise the result of zero weights) and the default may take
- * other block shapes.  Otherwise every ordered pair is gathered per row.
+ * of 128 or 256 below.  With grad_p NULL it does not form the
+ * potential-weight terms (with the same variant, bitwise the result of zero
+ * weights) and the default may take other block shapes.  Otherwise every
+ * ordered pair is gathered per row.
  */
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
                                    const float *grad_a, const float *grad_p,
@@ -177,9 +177,9 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
  * runs one persistent launch whose workgroups draw units largest-first from
  * a per-stream ticket counter (plus one launch that adds the pair-once
  * partial sums; about 16 (1 + M_s/2) N_s bytes of workspace per system of
- * N_s particles in M_s blocks).  Per-system results equal nbody_forces on that system
- * up to float32 summation order, and are bitwise independent of the other
- * systems' contents.
+ * N_s particles in M_s blocks).  Per-system results equal nbody_forces on
+ * that system up to float32 summation order, and are bitwise independent of
+ * the other systems' contents.
  *
  * Errors: num_systems < 0, NULL offsets, offsets[0] != 0, a decreasing
  * offset, a system or the total above NBODY_MAX_N -> INVALID_ARGUMENT; plus
