@@ -46,14 +46,27 @@ def test_two_streams_overlap(nb):
 
 def test_host_threads(nb):
     # two host threads, each on its own stream, each repeating forward,
-    # adjoint and batched calls
+    # adjoint, batched and leap-frog calls
     dev = need_gpu()
     x, m = _case(30000, 10, dev)
     g = to_dev(inputs.normal((30000, 3), (74, 11)), dev)
     ens = inputs.ensemble([300, 1000, 37, 2048], key=(74, 12))
     xe, me = to_dev(ens.x, dev), to_dev(ens.m, dev)
+    v = to_dev(inputs.normal((30000, 3), (74, 13)), dev) * 0.1
+    a0, _ = nb.forces(x, m, 1e-4, potential=False)
+
+    def leapfrog():
+        # three device-resident steps and the reverse sweep over them
+        xs, vs, as_ = x.clone(), v.clone(), a0.clone()
+        pos = torch.empty((4,) + tuple(x.shape), device=dev)
+        pos[0].copy_(x)
+        nb.leapfrog_(xs, vs, as_, m, 1e-4, 1e-3, 3, x_hist=pos[1:])
+        lx, lv, lm = g.clone(), g.clone(), torch.zeros_like(m)
+        nb.leapfrog_adjoint_(pos, m, 1e-4, 1e-3, lx, lv, lm, flags=3)
+        return xs, vs, lx, lv, lm
+
     ref = (nb.forces(x, m, 1e-4), nb.forces_backward(x, m, 1e-4, g, None),
-           nb.forces_batched(xe, me, ens.offsets, ens.eps2))
+           nb.forces_batched(xe, me, ens.offsets, ens.eps2), leapfrog())
     torch.cuda.synchronize()
     errors = []
 
@@ -63,7 +76,7 @@ def test_host_threads(nb):
             with torch.cuda.stream(s):
                 for _ in range(5):
                     got = (nb.forces(x, m, 1e-4), nb.forces_backward(x, m, 1e-4, g, None),
-                           nb.forces_batched(xe, me, ens.offsets, ens.eps2))
+                           nb.forces_batched(xe, me, ens.offsets, ens.eps2), leapfrog())
                     s.synchronize()
                     for pair_got, pair_ref in zip(got, ref):
                         for t_got, t_ref in zip(pair_got, pair_ref):
