@@ -280,6 +280,96 @@ def size_sweep(nb, torch, dev, inputs, metrics):
     return table
 
 
+def adjoint_leg(nb, torch, dev, inputs, metrics, peak):
+    """The adjoint at N = 16,384 with upstream weights on a and p: (its
+    workload, the JSON record)."""
+    log("adjoint leg")
+    wa = inputs.adjoint_16k()
+    xa = torch.from_numpy(wa.x).to(dev)
+    ma = torch.from_numpy(wa.m).to(dev)
+    ga = torch.from_numpy(wa.extra["w"]).to(dev)
+    gp = torch.from_numpy(wa.extra["v"]).to(dev)
+    gx = torch.empty_like(xa)
+    gm = torch.empty_like(ma)
+    bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
+    warm_up(bwd, torch)
+    wall_a, ka, ca = timed_calls(bwd, 50, torch, nb)
+    pa = metrics.pairs(wa.n)
+    rec = {
+        "workload": wa.name, "ms_per_call": wall_a * 1e3 / 50, "pairs_per_s": pa / (wall_a / 50),
+        "pair_kernel_ms": ka, "kernels_ms": ca,
+        "pairs_per_s_kernels": pa / (ca * 1e-3),
+        "frac_fp32_peak_38flop": pa / (ca * 1e-3) * 38 / (peak * 1e12),
+        "frac_fp32_peak_own_flop": pa / (ca * 1e-3) * 68 / (peak * 1e12),
+        "own_flop_per_pair": 68,
+        "variant": nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)],
+    }
+    log(f"adjoint {ca:.3f} ms (kernels)")
+    return wa, rec
+
+
+def batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons: bool = True):
+    """The 4,096-system ensemble in one persistent launch, tuned on the
+    ensemble first; with ``comparisons`` also the plain per-system launches
+    and their HIP-graph replay."""
+    log("batched leg")
+    ens = inputs.ensemble_4096()
+    xb = torch.from_numpy(ens.x).to(dev)
+    mb = torch.from_numpy(ens.m).to(dev)
+    ab = torch.empty_like(xb)
+    pb = torch.empty_like(mb)
+    t0 = time.perf_counter()
+    nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    bnames = nb.variant_names(nb.BATCHED)
+    mean_n = int(ens.offsets[-1]) // ens.num_systems
+    default_b = bnames[nb.selected_variant(nb.BATCHED, mean_n)]
+    # the persistent launch is tuned on this ensemble: every batched
+    # variant timed, the fastest kept for its mean system size
+    t0 = time.perf_counter()
+    tuned_b = nb.autotune_batched(xb, mb, ens.offsets, ens.eps2) if comparisons else None
+    tune_s = time.perf_counter() - t0
+    bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
+    warm_up(bat, torch)
+    wall_b, kbm, kb = timed_calls(bat, 10, torch, nb)
+    pb_pairs = metrics.pairs_ensemble(ens.sizes())
+    rec = {
+        "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
+        "pairs": pb_pairs, "persistent_ms": kb, "persistent_pair_kernel_ms": kbm,
+        "ms_per_call": wall_b * 1e3 / 10, "pairs_per_s": pb_pairs / (kb * 1e-3),
+        "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
+        "plan_build_s": plan_s,
+        "variant": bnames[nb.selected_variant(nb.BATCHED, mean_n)],
+        "default_variant": default_b,
+    }
+    if not comparisons:
+        return rec
+    views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
+             for lo, hi in zip(ens.offsets[:-1], ens.offsets[1:]) if hi > lo]
+
+    def plain():
+        for xs, ms, as_, ps in views:
+            nb.forces(xs, ms, ens.eps2, out=(as_, ps))
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    graph_ms = graph_plain_ms(plain, ab, pb, torch)
+    rec.update({
+        "plain_launches_ms": wall_plain * 1e3,
+        "speedup_vs_plain": wall_plain * 1e3 / kb,
+        "graph_plain_launches_ms": graph_ms,
+        "speedup_vs_graph": (graph_ms / kb) if graph_ms else None,
+        "autotuned": True, "autotune_s": tune_s, "tuned_variant": bnames[tuned_b],
+    })
+    log(f"batched {kb:.3f} ms vs plain {wall_plain * 1e3:.1f} ms")
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +380,9 @@ def main() -> int:
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the legs, time the paper's three unrolling programs and "
                          "the default variant over a range of N (pairs/s vs N)")
+    ap.add_argument("--only-leg", choices=("adjoint", "batched"),
+                    help="run only this leg and print its record (for profiling its kernel; "
+                         "the batched leg then skips the tuner and the per-system launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES (the reference "
                          "kernel that scales the HBM byte counters)")
@@ -311,6 +404,15 @@ def main() -> int:
     if args.size_sweep:
         print(json.dumps({"size_sweep": size_sweep(nb, torch, dev, inputs, metrics),
                           "unit": "pair-interactions/s", "data": "synthetic"}), flush=True)
+        return 0
+
+    if args.only_leg:
+        peak = metrics.MI355X_FP32_VECTOR_TFLOPS
+        if args.only_leg == "adjoint":
+            rec = adjoint_leg(nb, torch, dev, inputs, metrics, peak)[1]
+        else:
+            rec = batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons=False)
+        print(json.dumps({args.only_leg: rec}), flush=True)
         return 0
 
     if args.copy_calibration:
@@ -392,28 +494,7 @@ def main() -> int:
 
     if not args.only_forward:
         # ------------------------------------------------------ adjoint, 16k
-        log("adjoint leg")
-        wa = inputs.adjoint_16k()
-        xa = torch.from_numpy(wa.x).to(dev)
-        ma = torch.from_numpy(wa.m).to(dev)
-        ga = torch.from_numpy(wa.extra["w"]).to(dev)
-        gp = torch.from_numpy(wa.extra["v"]).to(dev)
-        gx = torch.empty_like(xa)
-        gm = torch.empty_like(ma)
-        bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
-        warm_up(bwd, torch)
-        wall_a, ka, ca = timed_calls(bwd, 50, torch, nb)
-        pa = metrics.pairs(wa.n)
-        out["adjoint"] = {
-            "workload": wa.name, "ms_per_call": wall_a * 1e3 / 50, "pairs_per_s": pa / (wall_a / 50),
-            "pair_kernel_ms": ka, "kernels_ms": ca,
-            "pairs_per_s_kernels": pa / (ca * 1e-3),
-            "frac_fp32_peak_38flop": pa / (ca * 1e-3) * 38 / (peak * 1e12),
-            "frac_fp32_peak_own_flop": pa / (ca * 1e-3) * 68 / (peak * 1e12),
-            "own_flop_per_pair": 68,
-            "variant": nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)],
-        }
-        log(f"adjoint {ca:.3f} ms (kernels)")
+        wa, out["adjoint"] = adjoint_leg(nb, torch, dev, inputs, metrics, peak)
 
         # ------------------------------------------- leap-frog with checkpoints
         log("leap-frog leg")
@@ -443,61 +524,11 @@ def main() -> int:
         out["leapfrog_grad"] = {"workload": wa.name + "_64steps_dt1e-3_ckpt8", "seconds": lf_s,
                                 "seconds_without_graphs": lf_times[False],
                                 "force_evals": f_evals, "vjp_evals": 64,
-                                "pairs_per_s": (f_evals + 64) * pa / lf_s}
+                                "pairs_per_s": (f_evals + 64) * metrics.pairs(wa.n) / lf_s}
         log(f"leap-frog gradient {lf_s * 1e3:.1f} ms")
 
         # ------------------------------------------------------ batched
-        log("batched leg")
-        ens = inputs.ensemble_4096()
-        xb = torch.from_numpy(ens.x).to(dev)
-        mb = torch.from_numpy(ens.m).to(dev)
-        ab = torch.empty_like(xb)
-        pb = torch.empty_like(mb)
-        t0 = time.perf_counter()
-        nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
-        torch.cuda.synchronize()
-        plan_s = time.perf_counter() - t0
-        bnames = nb.variant_names(nb.BATCHED)
-        mean_n = int(ens.offsets[-1]) // ens.num_systems
-        default_b = bnames[nb.selected_variant(nb.BATCHED, mean_n)]
-        # the persistent launch is tuned on this ensemble: every batched
-        # variant timed, the fastest kept for its mean system size
-        t0 = time.perf_counter()
-        tuned_b = nb.autotune_batched(xb, mb, ens.offsets, ens.eps2)
-        tune_s = time.perf_counter() - t0
-        bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
-        warm_up(bat, torch)
-        wall_b, kbm, kb = timed_calls(bat, 10, torch, nb)
-        views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
-                 for lo, hi in zip(ens.offsets[:-1], ens.offsets[1:]) if hi > lo]
-
-        def plain():
-            for xs, ms, as_, ps in views:
-                nb.forces(xs, ms, ens.eps2, out=(as_, ps))
-
-        plain()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain()
-        torch.cuda.synchronize()
-        wall_plain = time.perf_counter() - t0
-        graph_ms = graph_plain_ms(plain, ab, pb, torch)
-        pb_pairs = metrics.pairs_ensemble(ens.sizes())
-        out["batched"] = {
-            "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
-            "pairs": pb_pairs, "persistent_ms": kb, "persistent_pair_kernel_ms": kbm,
-            "ms_per_call": wall_b * 1e3 / 10, "pairs_per_s": pb_pairs / (kb * 1e-3),
-            "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
-            "plain_launches_ms": wall_plain * 1e3,
-            "speedup_vs_plain": wall_plain * 1e3 / kb,
-            "graph_plain_launches_ms": graph_ms,
-            "speedup_vs_graph": (graph_ms / kb) if graph_ms else None,
-            "plan_build_s": plan_s,
-            "variant": bnames[nb.selected_variant(nb.BATCHED, mean_n)],
-            "autotuned": True, "autotune_s": tune_s, "tuned_variant": bnames[tuned_b],
-            "default_variant": default_b,
-        }
-        log(f"batched {kb:.3f} ms vs plain {wall_plain * 1e3:.1f} ms")
+        out["batched"] = batched_leg(nb, torch, dev, inputs, metrics, peak)
 
     if not args.only_forward:
         # -------------------- the paper's unrolling programs (Sec. IV, Fig. p)
