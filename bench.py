@@ -12,8 +12,9 @@ Sec. V-A, the roofline position of the forward kernel, and the FP64 CPU
 reference timed on a bounded sample of the same workload on this host's
 cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --size-sweep     (pairs/s against N instead of the legs)
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-forward]
+       python bench.py --size-sweep               (pairs/s against N instead of the legs)
+       python bench.py --only-leg adjoint|batched (one leg alone, for profiling its kernel)
 """
 
 from __future__ import annotations
