@@ -35,39 +35,81 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-interactions/s & % FP32 VALU peak (38 flop/pair): fwd, adjoint, batched"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_plummer_n1048576_traffic.txt")
-FORWARD_SOURCES = [os.path.join(ROOT, "paper_0904_3659_amd", "csrc", f)
-                   for f in ("forward_sym.hip", "pair_once.hpp", "pair_term.hpp")]
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "forward_plummer_n1048576_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_0904_3659_amd", "csrc")
+# Files that define each leg's pair kernel; a counter summary is used only
+# while their hash matches the one it was taken on.
+KERNEL_SOURCES = {
+    "forward": ("forward_sym.hip", "pair_once.hpp", "pair_term.hpp"),
+    "adjoint": ("backward.hip", "pair_once.hpp"),
+    "batched": ("batched.hip", "pair_once.hpp", "pair_term.hpp"),
+}
+COUNTER_FILES = {
+    "forward": os.path.join(PROFILES, "forward_plummer_n1048576_valu_counters.txt"),
+    "adjoint": os.path.join(PROFILES, "adjoint_plummer_n16384_valu_counters.txt"),
+    "batched": os.path.join(PROFILES, "batched_ensemble4096_valu_counters.txt"),
+}
+# Tolerances of the float32 path against the FP64 oracle (max relative
+# error on |a_i|, the vector a_i and p_i; adjoint: normwise).
+TOL = 1e-4
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def forward_source_sha() -> str:
+def source_sha(kind: str = "forward") -> str:
     h = hashlib.sha256()
-    for f in FORWARD_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES[kind]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(variant: str):
-    """HBM bytes per launch of the forward kernel from the committed counter
-    summary, or None if absent, taken on another variant, or taken on a
-    different source of the pair-once kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def forward_source_sha() -> str:
+    return source_sha("forward")
+
+
+def read_keys(path: str) -> dict:
+    """The 'key: value' lines of a profile summary (comment lines skipped)."""
     kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha") != forward_source_sha() or kv.get("variant") != variant:
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def keyed_figure(path: str, kind: str, variant: str, key: str):
+    """Figure ``key`` of a committed profile summary, or None if the summary
+    is absent, was taken on another variant, or on another source of the
+    kernel."""
+    kv = read_keys(path)
+    if kv.get("kernel_source_sha") != source_sha(kind) or kv.get("variant") != variant:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(variant: str):
+    """HBM bytes per evaluation of the forward pair kernel(s) from the
+    committed counter summary (None if stale, see keyed_figure)."""
+    return keyed_figure(TRAFFIC_FILE, "forward", variant, "hbm_bytes_per_launch")
+
+
+def hw_flop(kind: str, variant: str):
+    """FP32 operations per call counted by the hardware (SQ_INSTS_VALU_*_F32
+    x 64 lanes, an FMA counting 2) from the committed counter summary, or
+    None if stale."""
+    return keyed_figure(COUNTER_FILES[kind], kind, variant, "hw_fp32_flop_per_call")
+
+
+def frac_hw(kind: str, variant: str, kernel_ms: float, peak: float):
+    f = hw_flop(kind, variant)
+    return None if f is None else f / (kernel_ms * 1e-3) / (peak * 1e12)
 
 
 def _sclk_path(torch, dev):
@@ -171,19 +213,26 @@ def timed_calls(fn, reps: int, torch, nb, events_in_timed_loop: bool = False):
     return wall, main_ms, total_ms
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
+def cpu_baseline(w, budget_s: float = 12.0, keep: bool = False):
     """The FP64 oracle, as it stands, on a bounded row sample of the same
-    workload: chunks of seeded rows until about ``budget_s`` seconds."""
+    workload: chunks of seeded rows until about ``budget_s`` seconds.
+
+    With ``keep`` the oracle's rows are returned too, as (record, rows,
+    a_rows, p_rows), so that the timed GPU result can be checked on them."""
     from oracle import reference as R
     from paper_0904_3659_amd import inputs
     n = w.n
     rows = inputs.check_rows(n, 65536, (3, 3))
     done, chunk, spent = 0, 256, 0.0
+    a_parts, p_parts = [], []
     while done < rows.size and spent < budget_s:
         part = rows[done:done + chunk]
         t0 = time.perf_counter()
-        R.forces_rows(w.x, w.m, w.eps2, part)
+        ar, pr = R.forces_rows(w.x, w.m, w.eps2, part)
         spent += time.perf_counter() - t0
+        if keep:
+            a_parts.append(ar)
+            p_parts.append(pr)
         done += part.size
         chunk = min(chunk * 2, 8192)
     pairs = done * (n - 1)
@@ -208,11 +257,80 @@ def cpu_baseline(w, budget_s: float = 12.0):
                          None)
     except OSError:
         pass
-    return {"value": pairs / spent, "unit": "pair-interactions/s", "cores": threads,
-            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
-            "sample": f"{done} seeded rows x {n - 1} j of {w.name}, FP64, {spent:.2f} s",
-            "single_thread_value": done1 * (n - 1) / spent1,
-            "single_thread_sample": f"first {done1} of the same rows, 1 thread, {spent1:.2f} s"}
+    rec = {"value": pairs / spent, "unit": "pair-interactions/s", "cores": threads,
+           "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
+           "sample": f"{done} seeded rows x {n - 1} j of {w.name}, FP64, {spent:.2f} s",
+           "single_thread_value": done1 * (n - 1) / spent1,
+           "single_thread_sample": f"first {done1} of the same rows, 1 thread, {spent1:.2f} s"}
+    if not keep:
+        return rec
+    return rec, rows[:done], np.concatenate(a_parts), np.concatenate(p_parts)
+
+
+def rel_errors(a, p, a_ref, p_ref) -> dict:
+    """Max relative errors of (a, p) against float64 reference rows:
+    |.|a|-|a_ref|.|/|a_ref|, |a - a_ref|/|a_ref| and |p - p_ref|/p_ref."""
+    a = np.asarray(a, np.float64)
+    na = np.linalg.norm(a_ref, axis=1)
+    ok = na > 0
+    mag = np.abs(np.linalg.norm(a, axis=1) - na)[ok] / na[ok]
+    vec = np.linalg.norm(a - a_ref, axis=1)[ok] / na[ok]
+    out = {"a_mag": float(mag.max()) if mag.size else 0.0,
+           "a_vec": float(vec.max()) if vec.size else 0.0}
+    if p is not None:
+        pos = p_ref > 0
+        pe = np.abs(np.asarray(p, np.float64) - p_ref)[pos] / p_ref[pos]
+        out["p"] = float(pe.max()) if pe.size else 0.0
+    out["max"] = max(out.values())
+    return out
+
+
+def oracle_checks(held: dict) -> dict:
+    """Compare the results the timed legs left behind (host copies in
+    ``held``) with the FP64 oracle.  Runs inside the CPU-baseline leg, the
+    only part of this script that calls the oracle."""
+    from oracle import reference as R
+    checks = {}
+    if "sizes" in held:
+        for name, (w, a, p) in held["sizes"].items():
+            if w.n <= 4096:
+                ar, pr = R.forces(w.x, w.m, w.eps2)
+                checks[name] = rel_errors(a, p, ar, pr)
+            else:
+                rows = np.arange(0, w.n, max(1, w.n // 1024))
+                ar, pr = R.forces_rows(w.x, w.m, w.eps2, rows)
+                checks[name] = rel_errors(a[rows], p[rows], ar, pr)
+                checks[name]["rows"] = int(rows.size)
+    if "adjoint" in held:
+        wa, gx, gm = held["adjoint"]
+        rx, rm = R.forces_vjp(wa.x, wa.m, wa.eps2, wa.extra["w"], wa.extra["v"])
+        ex = float(np.abs(gx - rx).max() / np.abs(rx).max())
+        em = float(np.abs(gm - rm).max() / np.abs(rm).max())
+        checks[wa.name] = {"grad_x_normwise": ex, "grad_m_normwise": em, "max": max(ex, em)}
+    if "batched" in held:
+        ens, a, p = held["batched"]
+        sizes = ens.sizes()
+        g = np.random.default_rng(11)
+        pick = np.unique(np.concatenate([
+            g.choice(ens.num_systems, min(192, ens.num_systems), replace=False),
+            [int(np.argmax(sizes)), int(np.argmin(np.where(sizes > 1, sizes, 1 << 30)))]]))
+        worst = {"a_mag": 0.0, "a_vec": 0.0, "p": 0.0, "max": 0.0}
+        for s in pick:
+            lo, hi = int(ens.offsets[s]), int(ens.offsets[s + 1])
+            if hi - lo < 2:
+                continue
+            ar, pr = R.forces(ens.x[lo:hi], ens.m[lo:hi], ens.eps2)
+            e = rel_errors(a[lo:hi], p[lo:hi], ar, pr)
+            worst = {k: max(worst[k], e[k]) for k in worst}
+        worst["systems_checked"] = int(pick.size)
+        checks[ens.name] = worst
+    if "unroll" in held:
+        xu, mu, e2, res = held["unroll"]
+        rows = np.arange(0, xu.shape[0], max(1, xu.shape[0] // 512))
+        ar, pr = R.forces_rows(xu, mu, e2, rows)
+        for label, (a, p) in res.items():
+            checks["unroll_study_n100000 " + label] = rel_errors(a[rows], p[rows], ar, pr)
+    return checks
 
 
 def graph_plain_ms(plain, ab, pb, torch):
@@ -281,9 +399,10 @@ def size_sweep(nb, torch, dev, inputs, metrics):
     return table
 
 
-def adjoint_leg(nb, torch, dev, inputs, metrics, peak):
+def adjoint_leg(nb, torch, dev, inputs, metrics, peak, held=None):
     """The adjoint at N = 16,384 with upstream weights on a and p: (its
-    workload, the JSON record)."""
+    workload, the JSON record).  With ``held`` a host copy of the result is
+    kept there for the oracle check."""
     log("adjoint leg")
     wa = inputs.adjoint_16k()
     xa = torch.from_numpy(wa.x).to(dev)
@@ -295,21 +414,32 @@ def adjoint_leg(nb, torch, dev, inputs, metrics, peak):
     bwd = lambda: nb.forces_backward(xa, ma, wa.eps2, ga, gp, out=(gx, gm))
     warm_up(bwd, torch)
     wall_a, ka, ca = timed_calls(bwd, 50, torch, nb)
+    variant = nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)]
     pa = metrics.pairs(wa.n)
+    ev = metrics.evaluated_pairs(pa, variant)
+    own = metrics.ADJOINT_FLOP_PER_PAIR
     rec = {
         "workload": wa.name, "ms_per_call": wall_a * 1e3 / 50, "pairs_per_s": pa / (wall_a / 50),
         "pair_kernel_ms": ka, "kernels_ms": ca,
         "pairs_per_s_kernels": pa / (ca * 1e-3),
-        "frac_fp32_peak_38flop": pa / (ca * 1e-3) * 38 / (peak * 1e12),
-        "frac_fp32_peak_own_flop": pa / (ca * 1e-3) * 68 / (peak * 1e12),
-        "own_flop_per_pair": 68,
-        "variant": nb.variant_names(nb.BACKWARD)[nb.selected_variant(nb.BACKWARD, wa.n)],
+        "evaluated_pairs": ev,
+        # fractions of the FP32 peak on the interactions the pair kernel
+        # evaluates, at the adjoint's own 68 flop and at the forward's 38
+        "frac_fp32_peak_own_flop": ev * own / (ka * 1e-3) / (peak * 1e12),
+        "frac_fp32_peak_38flop": ev * 38 / (ka * 1e-3) / (peak * 1e12),
+        "frac_hw": frac_hw("adjoint", variant, ka, peak),
+        "own_flop_per_pair": own,
+        "variant": variant,
     }
-    log(f"adjoint {ca:.3f} ms (kernels)")
+    if held is not None:
+        torch.cuda.synchronize()
+        held["adjoint"] = (wa, gx.cpu().numpy().astype(np.float64),
+                           gm.cpu().numpy().astype(np.float64))
+    log(f"adjoint {ka:.3f} ms pair kernel, {ca:.3f} ms with its reduction")
     return wa, rec
 
 
-def batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons: bool = True):
+def batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons: bool = True, held=None):
     """The 4,096-system ensemble in one persistent launch, tuned on the
     ensemble first; with ``comparisons`` also the plain per-system launches
     and their HIP-graph replay."""
@@ -334,16 +464,24 @@ def batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons: bool = True)
     bat = lambda: nb.forces_batched(xb, mb, ens.offsets, ens.eps2, out=(ab, pb))
     warm_up(bat, torch)
     wall_b, kbm, kb = timed_calls(bat, 10, torch, nb)
+    variant = bnames[nb.selected_variant(nb.BATCHED, mean_n)]
     pb_pairs = metrics.pairs_ensemble(ens.sizes())
+    ev = metrics.evaluated_pairs(pb_pairs, variant)
     rec = {
         "workload": ens.name, "systems": ens.num_systems, "particles": int(ens.offsets[-1]),
-        "pairs": pb_pairs, "persistent_ms": kb, "persistent_pair_kernel_ms": kbm,
+        "pairs": pb_pairs, "evaluated_pairs": ev,
+        "persistent_ms": kb, "persistent_pair_kernel_ms": kbm,
         "ms_per_call": wall_b * 1e3 / 10, "pairs_per_s": pb_pairs / (kb * 1e-3),
-        "frac_fp32_peak_38flop": pb_pairs / (kb * 1e-3) * 38 / (peak * 1e12),
+        "frac_fp32_peak_38flop": ev * 38 / (kbm * 1e-3) / (peak * 1e12),
+        "frac_hw": frac_hw("batched", variant, kbm, peak),
         "plan_build_s": plan_s,
-        "variant": bnames[nb.selected_variant(nb.BATCHED, mean_n)],
+        "variant": variant,
         "default_variant": default_b,
     }
+    if held is not None:
+        torch.cuda.synchronize()
+        held["batched"] = (ens, ab.cpu().numpy().astype(np.float64),
+                           pb.cpu().numpy().astype(np.float64))
     if not comparisons:
         return rec
     views = [(xb[lo:hi], mb[lo:hi], ab[lo:hi], pb[lo:hi])
@@ -440,12 +578,17 @@ def main() -> int:
     log(f"forward timed x{args.steps}")
     with SclkSampler(torch, dev) as clk:
         wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb, events_in_timed_loop=True)
+    # host copy of the last timed result, checked against the oracle below
+    a_last = a.cpu().numpy().astype(np.float64)
+    p_last = p.cpu().numpy().astype(np.float64)
     pairs = metrics.pairs(w.n)
     ms_step = wall * 1e3 / args.steps
     value = pairs / (wall / args.steps)
-    achieved = pairs * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3) / 1e12
     peak = metrics.MI355X_FP32_VECTOR_TFLOPS
     variant = nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, w.n)]
+    evaluated = metrics.evaluated_pairs(pairs, variant)
+    # algorithmic rate of the pair kernel: 38 flop per interaction it evaluates
+    achieved = evaluated * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3) / 1e12
     traffic = read_traffic(variant)
     log(f"forward {ms_step:.2f} ms/step, {value:.3e} pairs/s, kernel {kern_ms:.2f} ms")
 
@@ -464,38 +607,56 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "eps2": w.eps2, "pairs_per_step": pairs,
                    "variant": variant},
-        "frac_fp32_peak_38flop": value * metrics.FLOP_PER_PAIR / (peak * 1e12),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": variant, "kernel_ms": kern_ms, "call_kernels_ms": call_ms,
                      "flop_per_pair": metrics.FLOP_PER_PAIR,
+                     "evaluated_pairs": evaluated,
+                     # FP32 operations the hardware counted for this kernel
+                     # (committed rocprofv3 counters, same source and variant)
+                     "frac_hw": frac_hw("forward", variant, kern_ms, peak),
+                     # the rate at which ordered-pair terms are delivered, priced
+                     # at 38 flop each: what an every-ordered-pair kernel would
+                     # need to reach the same time; exceeds 1 for pair-once
+                     "frac_effective_ordered": pairs * metrics.FLOP_PER_PAIR / (kern_ms * 1e-3)
+                                               / (peak * 1e12),
                      # the peak scaled to the clock the driver reported while timing
                      "sclk_mhz_observed": clk.mean_mhz,
                      "frac_at_observed_sclk": (achieved / (peak * clk.mean_mhz / 2400.0)
                                                if clk.mean_mhz else None)},
     }
+    held = {}
 
     # ---------------------------------------------------------- other sizes
     if not args.only_forward:
         sizes = {}
+        held["sizes"] = {}
         for make in (inputs.plummer_1k, inputs.plummer_64k, inputs.cube_64k):
             ws = make()
             xs, ms_ = torch.from_numpy(ws.x).to(dev), torch.from_numpy(ws.m).to(dev)
-            f = lambda: nb.forces(xs, ms_, ws.eps2)
+            as_, ps = torch.empty_like(xs), torch.empty_like(ms_)
+            f = lambda: nb.forces(xs, ms_, ws.eps2, out=(as_, ps))
             warm_up(f, torch)
             reps = 50 if ws.n <= 4096 else 20
             wl, km, cm = timed_calls(f, reps, torch, nb)
             pr = metrics.pairs(ws.n)
+            vname = nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, ws.n)]
+            ev = metrics.evaluated_pairs(pr, vname)
             sizes[ws.name] = {"ms_per_call": wl * 1e3 / reps, "kernels_ms": cm, "pair_kernel_ms": km,
                               "pairs_per_s": pr / (wl / reps),
-                              "frac_fp32_peak_38flop_kernel": metrics.frac_of_fp32_peak(pr / (km * 1e-3)),
-                              "variant": nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, ws.n)]}
+                              "frac_fp32_peak_38flop_kernel": ev * 38 / (km * 1e-3) / (peak * 1e12),
+                              "variant": vname}
+            if ws.n <= 4096:
+                # latency-bound: the time per call is the figure of merit
+                sizes[ws.name]["latency_us_per_call"] = wl * 1e6 / reps
+            held["sizes"][ws.name] = (ws, as_.cpu().numpy().astype(np.float64),
+                                      ps.cpu().numpy().astype(np.float64))
             log(f"forward {ws.name}: {wl * 1e3 / reps:.4f} ms/call")
         out["forward_other_sizes"] = sizes
 
     if not args.only_forward:
         # ------------------------------------------------------ adjoint, 16k
-        wa, out["adjoint"] = adjoint_leg(nb, torch, dev, inputs, metrics, peak)
+        wa, out["adjoint"] = adjoint_leg(nb, torch, dev, inputs, metrics, peak, held)
 
         # ------------------------------------------- leap-frog with checkpoints
         log("leap-frog leg")
@@ -529,7 +690,7 @@ def main() -> int:
         log(f"leap-frog gradient {lf_s * 1e3:.1f} ms")
 
         # ------------------------------------------------------ batched
-        out["batched"] = batched_leg(nb, torch, dev, inputs, metrics, peak)
+        out["batched"] = batched_leg(nb, torch, dev, inputs, metrics, peak, held=held)
 
     if not args.only_forward:
         # -------------------- the paper's unrolling programs (Sec. IV, Fig. p)
@@ -537,21 +698,24 @@ def main() -> int:
         wu = inputs.paper_experiment_set(3)
         xu, mu = torch.from_numpy(wu[1]).to(dev), torch.from_numpy(wu[3]).to(dev)
         names = nb.variant_names(nb.FORWARD)
-        study = {}
+        study, res = {}, {}
         for label, vname in (("gpu-no-unrolling (K=1, U=1)", "fwd_b256_k1_u1"),
                              ("simple-unrolling (K=4, U=1)", "fwd_b256_k4_u1"),
                              ("double-unrolling (K=4, U=4)", "fwd_b256_k4_u4"),
                              ("default", None)):
             nb.set_variant(nb.FORWARD, names.index(vname) if vname else -1)
-            f = lambda: nb.forces(xu, mu, wu[4])
+            au, pu = torch.empty_like(xu), torch.empty_like(mu)
+            f = lambda: nb.forces(xu, mu, wu[4], out=(au, pu))
             warm_up(f, torch, 0.1, 1)
             wl, km, cm = timed_calls(f, 10, torch, nb)
             pr = metrics.pairs(xu.shape[0]) / (wl / 10)
             study[label] = {"variant": vname or names[nb.selected_variant(nb.FORWARD, xu.shape[0])],
                             "ms": wl * 100, "pairs_per_s": pr,
                             "gflops_38": pr * 38 / 1e9}
+            res[label] = (au.cpu().numpy().astype(np.float64), pu.cpu().numpy().astype(np.float64))
         nb.set_variant(nb.FORWARD, -1)
         out["unroll_study_n100000"] = study
+        held["unroll"] = (wu[1], wu[3], wu[4], res)
 
         # ---------------- Experiment 2 of the paper: 100 leap-frog steps
         log("paper experiment 2 stand-ins")
@@ -573,14 +737,29 @@ def main() -> int:
                           "speedup_vs_paper": paper_s[name] / secs}
         out["paper_experiment2_standins"] = exp2
 
+    ok = True
     if not args.no_cpu:
-        log("cpu baseline (FP64 oracle, bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(w)
+        # ------------------------------------ CPU baseline and oracle checks
+        log("cpu baseline (FP64 oracle, bounded sample) and oracle checks")
+        rec, rows, ar, pr = cpu_baseline(w, keep=True)
+        out["cpu_baseline"] = rec
+        err = rel_errors(a_last[rows], p_last[rows], ar, pr)
+        err["rows"] = int(rows.size)
+        out["max_rel_err"] = err["max"]
+        checks = {w.name + " (timed result)": err}
+        checks.update(oracle_checks(held))
+        out["oracle_checks"] = checks
+        out["oracle_tolerance"] = TOL
+        bad = {k: v["max"] for k, v in checks.items() if v["max"] > TOL}
+        if bad:
+            log(f"results differ from the FP64 oracle beyond {TOL}: {bad}")
+            ok = False
     else:
         out["cpu_baseline"] = None
+        out["max_rel_err"] = None
 
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

@@ -44,3 +44,26 @@ def test_traffic_figure_is_keyed_to_variant_and_sources():
     assert float(kv["hbm_bytes_per_launch"]) > float(kv["algorithmic_bytes_per_launch"]) > 0
     if kv["kernel_source_sha"] == bench.forward_source_sha():
         assert bench.read_traffic(kv["variant"]) == float(kv["hbm_bytes_per_launch"])
+
+
+def test_cpu_baseline_keeps_its_oracle_rows():
+    # the rows the CPU-baseline leg computes are the ones the bench checks
+    # the timed GPU result on: same row set, oracle values for each
+    n = 600
+    w = inputs.Workload("plummer_n600_test", inputs.plummer_positions(n, (90, 1)),
+                        inputs.lognormal_masses(n, (90, 2)), 1e-4)
+    rec, rows, ar, pr = bench.cpu_baseline(w, budget_s=0.2, keep=True)
+    assert rows.size > 0 and ar.shape == (rows.size, 3) and pr.shape == (rows.size,)
+    assert np.all(np.diff(rows) > 0)
+    # checked against themselves: zero error; a planted error is reported
+    e = bench.rel_errors(ar, pr, ar, pr)
+    assert e["max"] == 0.0
+    bad = ar.copy()
+    bad[rows.size // 2, 1] *= 1 + 3e-4
+    e = bench.rel_errors(bad, pr, ar, pr)
+    assert 1e-4 < e["max"] and e["a_vec"] > 1e-4
+
+
+def test_hw_flop_is_keyed_like_traffic():
+    for kind in ("forward", "adjoint", "batched"):
+        assert bench.hw_flop(kind, "no_such_variant") is None

@@ -313,3 +313,49 @@ def test_no_potential_kernel_same_acceleration(nb, n):
     a_p, p = nb.forces(x, m, 1e-4)
     a_n, none = nb.forces(x, m, 1e-4, potential=False)
     assert none is None and torch.equal(a_p, a_n)
+
+
+_PAIR_ONCE_REF = {}
+
+
+def _pair_once_case(n):
+    """Inputs and FP64 reference for the forced pair-once sweep: the full
+    oracle up to 10^4 bodies, 2,048 seeded rows above."""
+    if n not in _PAIR_ONCE_REF:
+        x = inputs.plummer_positions(n, (66, n))
+        m = inputs.lognormal_masses(n, (66, n, 1))
+        rows = None if n <= 16384 else inputs.check_rows(n, 2048, (66, n, 2))
+        if rows is None:
+            ar, pr = R.forces(x, m, 1e-4)
+        else:
+            ar, pr = R.forces_rows(x, m, 1e-4, rows)
+        _PAIR_ONCE_REF[n] = (x, m, rows, ar, pr)
+    return _PAIR_ONCE_REF[n]
+
+
+@pytest.mark.parametrize("n", [4097, 10257, (1 << 17) + 3])
+def test_every_pair_once_variant_with_and_without_potential(nb, n):
+    # Each pair-once forward kernel, forced, at a ragged size: the kernel
+    # without the potential (which skips its terms in the pair loop) must
+    # give the acceleration of the kernel with it bitwise, and both must
+    # meet the oracle.  The leap-frog runs the no-potential kernels.
+    dev = need_gpu()
+    x, m, rows, ar, pr = _pair_once_case(n)
+    xd, md = to_dev(x, dev), to_dev(m, dev)
+    names = nb.variant_names(nb.FORWARD)
+    sel = slice(None) if rows is None else rows
+    try:
+        for name in [nm for nm in names if nm.startswith("fwd_sym")]:
+            print(f"[pair-once sweep] {name} n={n}", flush=True)
+            nb.set_variant(nb.FORWARD, names.index(name))
+            a_p, p = nb.forces(xd, md, 1e-4)
+            a_n, none = nb.forces(xd, md, 1e-4, potential=False)
+            torch.cuda.synchronize()
+            assert none is None
+            assert torch.equal(a_p, a_n), f"{name} n={n}: a differs without the potential"
+            assert_parity(host(a_p)[sel], host(p)[sel], ar, pr, label=f"{name} n={n}")
+            # the no-potential kernel on its own against the oracle's a
+            e_mag, e_vec, _ = errors(host(a_n)[sel], pr, ar, pr)
+            assert e_mag <= 1e-4 and e_vec <= 1e-4, name
+    finally:
+        nb.set_variant(nb.FORWARD, -1)

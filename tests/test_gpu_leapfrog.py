@@ -256,3 +256,45 @@ def test_leapfrog_adjoint_call_equals_composed_calls(nb, n, variant, flags, step
     for g, r in zip(got, ref):
         assert torch.equal(g, r)
     assert not torch.equal(got[1], lv0)
+
+
+# ---------------------------------------------------------------------------
+# The stand-ins for the paper's Experiment 2 (Sec. V-A, Table II): 100
+# leap-frog steps at the paper's N, dt and softening (at 100,000 bodies as
+# many steps as keep the FP64 integrator near half a minute), the device
+# integrator against the FP64 one.
+#
+# Tolerance.  A float32 integrator differs from the float64 one by a
+# rounding of relative size 2^-24 in x (and v) at every step, plus the
+# float32 force error (~1e-6 relative, a 2^-24-sized change of x's effect at
+# these time steps).  The FP64 integrator's own response to one such
+# perturbation is measured on the spot: x0 nudged by 2^-24 relative (seeded
+# random signs), run over the same steps, S_x = max|dx_T| / max|x_T| and
+# S_v = max|dv_T| / max|v_T|.  With at most four such perturbations per step
+# (x rounded once, v twice, the force error), each growing no faster than
+# the first one, the float32 run stays within 4 * steps * S of the FP64 run.
+
+EXP2_STEPS = (100, 100, 100, 6)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_paper_experiment2_standins_against_fp64_integrator(nb, k):
+    from paper_0904_3659_amd import leapfrog as LF
+    dev = need_gpu()
+    name, x0, v0, m0, eps2, dt = inputs.paper_experiment_set(k)
+    steps = EXP2_STEPS[k]
+    print(f"[exp2] {name} n={x0.shape[0]} steps={steps} dt={dt} eps2={eps2}", flush=True)
+    xt, vt, mt = to_dev(x0, dev), to_dev(v0, dev), to_dev(m0, dev)
+    xg, vg, _ = LF.integrate(xt, vt, mt, eps2, dt, steps)
+    torch.cuda.synchronize()
+    xr, vr = R.leapfrog(x0, v0, m0, eps2, dt, steps)
+    sgn = inputs.rng(74, k).choice([-1.0, 1.0], size=x0.shape)
+    xq, vq = R.leapfrog(x0.astype(np.float64) * (1.0 + sgn * 2.0**-24), v0, m0, eps2, dt, steps)
+    s_x = np.abs(xq - xr).max() / np.abs(xr).max()
+    s_v = np.abs(vq - vr).max() / np.abs(vr).max()
+    e_x = np.abs(host(xg) - xr).max() / np.abs(xr).max()
+    e_v = np.abs(host(vg) - vr).max() / np.abs(vr).max()
+    tol_x, tol_v = 4 * steps * s_x, 4 * steps * s_v
+    print(f"[parity] {name}: x {e_x:.2e} (tol {tol_x:.2e}), v {e_v:.2e} (tol {tol_v:.2e}); "
+          f"FP64 spread x {s_x:.2e} v {s_v:.2e}", flush=True)
+    assert e_x <= tol_x and e_v <= tol_v
