@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 3
+#define NBODY_ABI_VERSION 4
 #define NBODY_MAX_N (INT64_C(1) << 28)
 #define NBODY_MAX_STEPS (INT64_C(1) << 30)
 
@@ -94,17 +94,19 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 3,000 <= n <= 2^21 the default variant evaluates each
+ * Kernels: for 3,000 <= n <= 2^24 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
- * force is antisymmetric in the pair); it needs about 8 n^2 / P bytes of
- * library workspace, with blocks of P = 2048 particles from 2^17 up
- * (4.3 GB at n = 2^20, 17 GB at 2^21), P = 1024 from 2^16, 256 from 12,000
- * and 128 below.  Outside that range the default gathers every ordered
- * pair per row with j-splits: below 3,000 in one launch whose last
- * workgroup per 64 rows adds the splits (16 n * splits bytes of workspace
- * and one int counter per 64 rows), above 2^21 with float64 row sums (as
- * NBODY_FORCES_F64_SUM below) and a reduction launch (at most
- * 32 n * splits bytes).
+ * force is antisymmetric in the pair), in blocks of P = 2048 particles from
+ * 2^17 up, 1024 from 2^16, 256 from 12,000 and 128 below.  Each block meets
+ * the blocks after it on a ring; the ring offsets run in groups, one launch
+ * per group, each followed by a launch that adds the group's partial sums
+ * to a float64 running sum per particle, so the library workspace stays at
+ * most 1 GiB up to n = 2^22 (256 n bytes above; 0.86 GiB at n = 2^20).
+ * Outside that range the default gathers every ordered pair per row with
+ * j-splits: below 3,000 in one launch whose last workgroup per 64 rows adds
+ * the splits (16 n * splits bytes of workspace and one int counter per 64
+ * rows), above 2^24 with float64 row sums (as NBODY_FORCES_F64_SUM below)
+ * and a reduction launch (at most 32 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
  *
@@ -130,9 +132,10 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
  * sums, and the j-split partials, are added in float64 and rounded to
  * float32 once at the store.  Float32 running sums add n / tile tile sums in
  * float32, an error that grows with n; the paper computes in single
- * precision throughout (Sec. IV).  The default already sums in float64
- * above 2^21; up to 2^21 the flag trades the pair-once (or one-launch)
- * kernel for the row gather (about 20% slower at n = 2^20) and
+ * precision throughout (Sec. IV).  The default pair-once kernel adds its
+ * partial sums in float64 across ring groups, and above 2^24 the default
+ * sums in float64 as this flag does; the flag trades the pair-once (or
+ * one-launch) kernel for the row gather (about 30% slower at n = 2^20) and
  * 32 n * splits bytes of workspace.  A forced variant (nbody_set_variant)
  * is honoured only if it is one of the "_f64sum" variants.
  * Errors: as nbody_forces; unknown flag bits -> INVALID_ARGUMENT.
@@ -152,11 +155,11 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
  * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
- * Kernels: for 2^11 <= n <= 2^20 the default variant evaluates each
- * unordered pair once (the x-gradient term is antisymmetric in the pair)
- * with about 8 n^2 / P bytes of workspace, for blocks of P = 1024
- * particles from 2^16 (8.6 GB at n = 2^20; from 2^17 without grad_p) and
- * of 128 or 256 below.  With grad_p NULL it does not form the
+ * Kernels: for 2^11 <= n <= 2^24 the default variant evaluates each
+ * unordered pair once (the x-gradient term is antisymmetric in the pair),
+ * for blocks of P = 1024 particles from 2^16 (from 2^17 without grad_p)
+ * and of 128 or 256 below, with the ring groups and bounded workspace of
+ * the pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it does not form the
  * potential-weight terms (with the same variant, bitwise the result of zero
  * weights) and the default may take other block shapes.  Otherwise every
  * ordered pair is gathered per row.
@@ -314,6 +317,27 @@ nbody_status nbody_autotune_batched(const int64_t *offsets, int64_t num_systems,
                                     const float *m, float eps2, void *stream);
 
 /*
+ * The launch plan of variant `index` of NBODY_KIND_FORWARD or
+ * NBODY_KIND_BACKWARD at size n, computed on the host from the arguments
+ * alone (no device is touched): returns the bytes of library workspace one
+ * call needs on a device of num_cu compute units where the variant's pair
+ * kernel fits blocks_per_cu workgroups per CU, and sets *timed (if not NULL)
+ * to whether nbody_autotune would time the variant there with free_bytes
+ * of free device memory.  The timer times a variant only if n lies in its
+ * size band (the one-launch forward kernels stop at 2^16) and its workspace
+ * fits the smaller of NBODY_TUNE_WORKSPACE_CAP bytes (environment; default
+ * 2 GiB) and a quarter of the free memory; a variant whose allocation fails
+ * while timing is skipped as well, and the workspace the timing grew on the
+ * stream is given back when it ends.  The pair-once variants bound their
+ * workspace by running their ring of block offsets in several launches: at
+ * most 1 GiB (or 256 n bytes where n > 2^22).
+ * Returns -1 for an unknown kind or index, n outside [0, NBODY_MAX_N],
+ * num_cu or blocks_per_cu below 1, free_bytes below 0.
+ */
+int64_t nbody_variant_plan(int kind, int index, int64_t n, int num_cu, int blocks_per_cu,
+                           int64_t free_bytes, int *timed);
+
+/*
  * Variant index the library would use for `kind` at size n (-1 on error);
  * for NBODY_KIND_BACKWARD the choice for a call with grad_p given (without
  * it, and in nbody_leapfrog_adjoint, the default can differ).
@@ -328,19 +352,22 @@ nbody_status nbody_release_workspace(void);
 /*
  * Kernel timing of the library's own launches.  While enabled (on != 0),
  * every successful nbody_forces / nbody_forces_backward /
- * nbody_forces_batched call of the calling thread records three HIP events
- * on its stream: before its pair kernel, after its pair kernel, and after
- * its last kernel (the partial-sum reduction, if any).  The last 256 calls
- * are kept.  Enabling or disabling clears the record.  Costs three event
- * records per call; off by default.
+ * nbody_forces_batched call (and each step of nbody_leapfrog and
+ * nbody_leapfrog_adjoint) of the calling thread records HIP events on its
+ * stream: before and after each of its pair kernels (a pair-once call
+ * launches one per ring group) and after its last kernel (the partial-sum
+ * fold, if any).  The last 256 calls are kept.  Enabling or disabling
+ * clears the record.  Costs two event records per pair kernel and one per
+ * call; off by default.
  */
 nbody_status nbody_profile_enable(int on);
 
 /*
- * Wait for the recorded calls of this thread and return the mean duration
- * of the pair kernel (main_ms) and of the whole call's kernels (total_ms)
- * over them, and their number (calls; 0 leaves the means at 0).  Clears the
- * record.  NULL outputs are skipped.
+ * Wait for the recorded calls of this thread and return the mean over them
+ * of the summed durations of a call's pair kernels (main_ms) and of the time
+ * from its first pair kernel's start to its last kernel's end (total_ms),
+ * and their number (calls; 0 leaves the means at 0).  Clears the record.
+ * NULL outputs are skipped.
  */
 nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls);
 

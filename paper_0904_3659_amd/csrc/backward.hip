@@ -252,7 +252,8 @@ struct SymBwdArgs {
     float eps2;
     int M;
     int C;
-    float4 *partial;  // [C + M/2][n]: (dL/dx, dL/dm)
+    int d_lo, d_hi;   // ring deltas of this launch's group
+    float4 *partial;  // [C + G][n]: (dL/dx, dL/dm)
 };
 
 // One unordered pair: adds F and the k mass term to tk; returns the j-side
@@ -495,25 +496,17 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
-    // this chunk's share of the block's tiles (diagonal first, then the ring
-    // delta-major); all-padding tiles are skipped (uniform)
-    const int U = TPB + ring_len(I, M) * TPB;
+    // this chunk's share of the block's tiles in the launch's ring group
+    // (diagonal first, then the ring delta-major); all-padding tiles are
+    // skipped (uniform)
+    const int d_lo = A.d_lo;
+    const int dj = group_first_delta(d_lo);
+    const int U = group_tiles(I, M, d_lo, A.d_hi, TPB);
     const int u0 = (int)((long long)U * c / C);
     const int u1 = (int)((long long)U * (c + 1) / C);
-    auto base_of = [&](int u, int &delta) {
-        if (u < TPB) {
-            delta = 0;
-            return I * PB + u * 64;
-        }
-        const int q = u - TPB;
-        delta = 1 + q / TPB;
-        int J = I + delta;
-        if (J >= M) J -= M;
-        return J * PB + (q - (delta - 1) * TPB) * 64;
-    };
     int u = u0, delta = 0, jbase = 0;
     for (; u < u1; ++u)
-        if ((jbase = base_of(u, delta)) < n) break;
+        if ((jbase = tile_base<PB>(u, I, M, d_lo, delta)) < n) break;
     float4 nxm = make_float4(0.f, 0.f, 0.f, 0.f), nwv = nxm;
     if (u < u1 && tid < 64) load_xw(A, jbase + tid, nxm, nwv);
 
@@ -530,7 +523,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         __syncthreads();
         const int cur_u = u, cur_delta = delta, cur_base = jbase;
         for (++u; u < u1; ++u)
-            if ((jbase = base_of(u, delta)) < n) break;
+            if ((jbase = tile_base<PB>(u, I, M, d_lo, delta)) < n) break;
         if (u < u1 && tid < 64) load_xw(A, jbase + tid, nxm, nwv);
 
         float4 tk[K];
@@ -564,7 +557,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                     sum.w += v.w;
                 }
                 const int j = cur_base + tid;
-                if (j < n) A.partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
+                if (j < n) A.partial[(size_t)(C + cur_delta - dj) * n + j] = sum;
             }
         } else if (wv == cur_u / K) {
             // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K);
@@ -598,63 +591,81 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 template <int W, int K, int OCC>
 nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
                               int n, float eps2, const float *ga, const float *gp, float *gx,
-                              float *gm, hipStream_t stream, const LfEpi *epi, bool *fused)
+                              float *gm, hipStream_t stream, const LfEpi *epi, bool *fused,
+                              const Arena &arena)
 {
     constexpr int PB = W * 64 * K;
-    const int M = (n + PB - 1) / PB;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, backward_sym_kernel<W, K, true>, W * 64, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
-    int C = per_cu * dev.num_cu / (M * OCC);
-    if (C < 1) C = 1;
-    const int max_c = (M / 2 + 1) * (PB / 64);
-    if (C > max_c) C = max_c;
-    const int slots = C + M / 2;
+    SymPlan pl;
+    if (!sym_plan(n, PB, (int64_t)per_cu * dev.num_cu, OCC, arena.budget(sym_workspace_budget(n)), &pl))
+        return fail(NBODY_ERROR_INVALID_ARGUMENT,
+                    "n = %d needs more than the %zu-byte workspace limit of %s", n,
+                    arena.budget(sym_workspace_budget(n)), name);
     void *ws = nullptr;
-    nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)slots * n, &ws);
+    nbody_status st = arena.get(dev, stream, pl.bytes(), &ws);
     if (st != NBODY_OK) return st;
-    SymBwdArgs A{x, m, ga, gp, n, eps2, M, C, static_cast<float4 *>(ws)};
+    float4 *partial = static_cast<float4 *>(ws);
+    double4 *acc = pl.acc_bytes ? reinterpret_cast<double4 *>(static_cast<char *>(ws) + pl.partial_bytes)
+                                : nullptr;
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
-    prof_mark(stream, 0);
-    if (gp)
-        hipLaunchKernelGGL((backward_sym_kernel<W, K, true>), dim3(M * C), dim3(W * 64), 0, stream,
-                           A);
-    else
-        hipLaunchKernelGGL((backward_sym_kernel<W, K, false>), dim3(M * C), dim3(W * 64), 0,
-                           stream, A);
-    prof_mark(stream, 1);
-    st = check_launch(name);
-    if (st != NBODY_OK) return st;
-    if (epi && epi->mode != kLfNone) {
-        hipLaunchKernelGGL((slot_reduce_kernel<PB, true>), dim3((n + 63) / 64), dim3(256), 0,
-                           stream, A.partial, n, M, C, gx, gm, *epi);
-        if (fused) *fused = true;
-    } else {
-        hipLaunchKernelGGL((slot_reduce_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
-                           A.partial, n, M, C, gx, gm, LfEpi{});
+    const bool lf = epi && epi->mode != kLfNone;
+    for (int g = 0; g < pl.groups; ++g) {
+        SymBwdArgs A{x, m, ga, gp, n, eps2, pl.M, pl.C, 0, 0, partial};
+        sym_group(pl, g, &A.d_lo, &A.d_hi);
+        prof_mark(stream, 0);
+        if (gp)
+            hipLaunchKernelGGL((backward_sym_kernel<W, K, true>), dim3(pl.M * pl.C), dim3(W * 64), 0,
+                               stream, A);
+        else
+            hipLaunchKernelGGL((backward_sym_kernel<W, K, false>), dim3(pl.M * pl.C), dim3(W * 64),
+                               0, stream, A);
+        prof_mark(stream, 1);
+        st = check_launch(name);
+        if (st != NBODY_OK) return st;
+        const int first = g == 0, last = g == pl.groups - 1;
+        if (last && lf)
+            hipLaunchKernelGGL((slot_fold_kernel<PB, true>), dim3((n + 63) / 64), dim3(256), 0,
+                               stream, partial, n, pl.M, pl.C, A.d_lo, A.d_hi, first, last, acc, gx,
+                               gm, *epi);
+        else
+            hipLaunchKernelGGL((slot_fold_kernel<PB>), dim3((n + 63) / 64), dim3(256), 0, stream,
+                               partial, n, pl.M, pl.C, A.d_lo, A.d_hi, first, last, acc, gx, gm,
+                               LfEpi{});
+        st = check_launch("slot_fold");
+        if (st != NBODY_OK) return st;
     }
-    return check_launch("slot_reduce");
+    if (lf && fused) *fused = true;
+    return NBODY_OK;
 }
 
 using KernelFn = void (*)(BwdArgs);
 
 using SymRunFn = nbody_status (*)(const char *, const Device &, const float *, const float *,
                                   int, float, const float *, const float *, float *, float *,
-                                  hipStream_t, const LfEpi *, bool *);
+                                  hipStream_t, const LfEpi *, bool *, const Arena &);
 
-// A gather variant (rows own all j) or, with sym set, a pair-once variant.
+using SymKernelFn = void (*)(SymBwdArgs);
+
+// A gather variant (rows own all j) or, with sym set, a pair-once variant
+// with W waves, K rows per lane and chunk divisor O.
 struct Variant {
     const char *name;
     int block, k, unroll;
     KernelFn direct, partial;
     SymRunFn sym;
+    SymKernelFn sym_kernel;
+    int sym_w, sym_k, sym_occ;
 };
 
 #define BWD_VARIANT(B, K, U) \
-    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr}
-#define BWD_SYM_VARIANT(W, K, O) {"bwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, O>}
+    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr, nullptr, 0, 0, 0}
+#define BWD_SYM_VARIANT(W, K, O) \
+    {"bwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, O>, \
+     backward_sym_kernel<W, K, true>, W, K, O}
 
 const Variant kVariants[] = {
     BWD_VARIANT(256, 2, 4),
@@ -695,7 +706,7 @@ static int variant_index(const char *name)
 }
 
 // Measured on MI355X: the pair-once adjoint wins from 2^11 particles on; its
-// partial buffer grows as 8 n^2 / P bytes (P = 128 to 1024), so above 2^20
+// workspace is bounded as the forward's (ring groups), and above 2^24
 // particles the gather kernel takes over.  Without potential weights
 // (grad_p NULL) each pair costs fewer registers and one-wave blocks of 128
 // particles lead from about 6,000 to 2^17 particles (5-12% ahead of the
@@ -709,7 +720,7 @@ int backward_default_variant(int64_t n, bool has_v)
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
-    if (n > (1 << 20)) return gather;
+    if (n > (1 << 24)) return gather;
     if (!has_v && n >= 6000 && n < (1 << 17)) return pair_once_nov;
     if (n >= (1 << 16)) return pair_once;
     if (has_v && n >= 14000) return pair_once_mid;
@@ -717,22 +728,68 @@ int backward_default_variant(int64_t n, bool has_v)
     return gather_small;
 }
 
-nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m, int n,
-                          float eps2, const float *ga, const float *gp, float *gx, float *gm,
-                          hipStream_t stream, const LfEpi *epi, bool *fused)
+// Geometry of the row gather: j-splits and j per split.
+static void bwd_gather_geometry(const Variant &V, int n, int num_cu, int *splits_out,
+                                int *chunk_out)
 {
-    const Variant &V = kVariants[variant];
-    if (fused) *fused = false;
-    if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream, epi, fused);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
-    const int target = 4 * dev.num_cu;
+    const int target = 4 * num_cu;
     const int max_splits = (n + V.block - 1) / V.block;
     int splits = (target + iblocks - 1) / iblocks;
     splits = splits < 1 ? 1 : (splits > max_splits ? max_splits : splits);
     int chunk = (n + splits - 1) / splits;
     chunk = (chunk + V.block - 1) / V.block * V.block;
-    splits = (n + chunk - 1) / chunk;
+    *splits_out = (n + chunk - 1) / chunk;
+    *chunk_out = chunk;
+}
+
+int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
+{
+    if (variant < 0 || variant >= kNumVariants || n < 0 || n > NBODY_MAX_N || num_cu < 1 ||
+        per_cu < 1)
+        return -1;
+    if (n == 0) return 0;
+    const Variant &V = kVariants[variant];
+    if (V.sym) {
+        SymPlan pl;
+        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu, V.sym_occ,
+                      sym_workspace_budget(n), &pl))
+            return -1;
+        return (int64_t)pl.bytes();
+    }
+    int splits = 1, chunk = 0;
+    bwd_gather_geometry(V, (int)n, num_cu, &splits, &chunk);
+    return splits > 1 ? (int64_t)sizeof(float4) * splits * n : 0;
+}
+
+int64_t backward_variant_max_n(int variant)
+{
+    return (variant < 0 || variant >= kNumVariants) ? -1 : NBODY_MAX_N;
+}
+
+nbody_status backward_variant_occupancy(int variant, int *per_cu)
+{
+    const Variant &V = kVariants[variant];
+    const hipError_t e =
+        V.sym ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.sym_kernel, V.sym_w * 64, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.partial, V.block, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (*per_cu < 1) *per_cu = 1;
+    return NBODY_OK;
+}
+
+nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m, int n,
+                          float eps2, const float *ga, const float *gp, float *gx, float *gm,
+                          hipStream_t stream, const LfEpi *epi, bool *fused, const Arena &arena)
+{
+    const Variant &V = kVariants[variant];
+    if (fused) *fused = false;
+    if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream, epi, fused, arena);
+    const int iblk = V.block * V.k;
+    const int iblocks = (n + iblk - 1) / iblk;
+    int splits = 1, chunk = 0;
+    bwd_gather_geometry(V, n, dev.num_cu, &splits, &chunk);
 
     BwdArgs P{x, m, ga, gp, n, eps2, chunk, nullptr, gx, gm};
     if (splits == 1) {
@@ -743,7 +800,7 @@ nbody_status backward_run(int variant, const Device &dev, const float *x, const 
         return check_launch(V.name);
     }
     void *ws = nullptr;
-    nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
+    nbody_status st = arena.get(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
     if (st != NBODY_OK) return st;
     P.partial = static_cast<float4 *>(ws);
     if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");

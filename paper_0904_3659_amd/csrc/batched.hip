@@ -132,7 +132,7 @@ __global__ __launch_bounds__(W * 64) void batched_sym_kernel(BatSymArgs A)
         const int ns = u.y;
         const int M = (ns + PB - 1) / PB;
         pair_once_block<W, K, true>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
-                                    A.partial + u.w, tile, jacc);
+                                    0, M / 2 + 1, A.partial + u.w, tile, jacc);
     }
 }
 
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(W * 64) void batched_sym_dyn_kernel(BatSymArgs A, i
         const int ns = u.y;
         const int M = (ns + PB - 1) / PB;
         pair_once_block<W, K, true>(A.x + 3 * (size_t)u.x, A.m + u.x, ns, A.eps2, M, u.z, 0, 1,
-                                    A.partial + u.w, tile, jacc);
+                                    0, M / 2 + 1, A.partial + u.w, tile, jacc);
     }
     if (threadIdx.x == 0) {
         // Every workgroup draws tickets until it fails once and only then

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -155,6 +156,43 @@ nbody_status workspace_aux(const Device &dev, hipStream_t stream, size_t bytes, 
     return grow_buffer(dev, stream, 1, bytes, ptr);
 }
 
+size_t workspace_size(const Device &dev, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto it = g_ws.find({dev.id, stream, 0});
+    return it == g_ws.end() ? 0 : it->second.bytes;
+}
+
+nbody_status workspace_trim(const Device &dev, hipStream_t stream, size_t bytes)
+{
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto it = g_ws.find({dev.id, stream, 0});
+    if (it == g_ws.end() || it->second.bytes <= bytes) return NBODY_OK;
+    Buffer &b = it->second;
+    hipError_t e = hipFree(b.ptr);  // waits for the device
+    b.ptr = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+    if (bytes == 0) return NBODY_OK;
+    e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        return hip_fail(e, "hipMalloc(workspace)");
+    }
+    b.bytes = bytes;
+    return NBODY_OK;
+}
+
+size_t tune_workspace_cap(size_t free_bytes)
+{
+    size_t cap = (size_t)2 << 30;
+    if (const char *env = std::getenv("NBODY_TUNE_WORKSPACE_CAP")) {
+        const unsigned long long v = std::strtoull(env, nullptr, 10);
+        if (v > 0) cap = (size_t)v;
+    }
+    return std::min(cap, free_bytes / 4);
+}
+
 namespace {
 struct CounterBuf {
     int *ptr = nullptr;
@@ -194,54 +232,113 @@ nbody_status counters(const Device &dev, hipStream_t stream, size_t count, int *
     return NBODY_OK;
 }
 
+nbody_status Arena::get(const Device &dev, hipStream_t stream, size_t bytes, void **ptr) const
+{
+    if (!base) return workspace(dev, stream, bytes, ptr);
+    if (bytes > cap)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT,
+                    "the call needs %zu bytes of workspace; the fixed region holds %zu", bytes, cap);
+    *ptr = base;
+    return NBODY_OK;
+}
+
+nbody_status Arena::get_counters(const Device &dev, hipStream_t stream, size_t count, int **ptr) const
+{
+    if (!base) return nbody::counters(dev, stream, count, ptr);
+    if (count > counter_count)
+        return fail(NBODY_ERROR_INVALID_ARGUMENT,
+                    "the call needs %zu counters; the fixed region holds %zu", count, counter_count);
+    *ptr = counters;
+    return NBODY_OK;
+}
+
 // ---------------------------------------------------------------- profiling
 
 namespace {
-constexpr int kProfSlots = 256;
+constexpr size_t kProfCalls = 256;
 std::atomic<bool> g_prof_on{false};
+// One recorded call: an event before and after each of its pair kernels
+// (a call may launch several), and one after its last kernel.
+struct ProfCall {
+    std::vector<hipEvent_t> pair;  // begin, end, begin, end, ...
+    hipEvent_t end = nullptr;
+};
 struct ProfState {
     int device = -1;
-    std::vector<hipEvent_t> ev;  // kProfSlots x 3
-    int next = 0;
-    int count = 0;
-    bool pending = false;  // mark 0 recorded for the current call
-    ~ProfState()
+    std::vector<hipEvent_t> pool;  // free events of `device`
+    std::deque<ProfCall> calls;    // finished calls, oldest first
+    ProfCall cur;                  // the call being recorded
+    bool pending = false;          // cur holds a pair kernel's events
+    void give(ProfCall &c)
     {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c.pair) pool.push_back(e);
+        if (c.end) pool.push_back(c.end);
+        c.pair.clear();
+        c.end = nullptr;
     }
+    void clear()
+    {
+        for (auto &c : calls) give(c);
+        calls.clear();
+        give(cur);
+        pending = false;
+    }
+    void destroy()
+    {
+        clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+    ~ProfState() { destroy(); }
 };
 thread_local ProfState t_prof;
-
-bool prof_ready()
-{
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
-    if (t_prof.device == dev && !t_prof.ev.empty()) return true;
-    for (hipEvent_t e : t_prof.ev) (void)hipEventDestroy(e);
-    t_prof.ev.assign(3 * kProfSlots, nullptr);
-    for (auto &e : t_prof.ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            t_prof.ev.clear();
-            return false;
-        }
-    t_prof.device = dev;
-    t_prof.next = 0;
-    t_prof.count = 0;
-    return true;
-}
 }  // namespace
 
 void prof_mark(hipStream_t stream, int which)
 {
-    if (!g_prof_on.load(std::memory_order_relaxed) || !prof_ready()) return;
-    if (which == 0) t_prof.pending = true;
-    if (!t_prof.pending) return;  // a call that launched no pair kernel is not recorded
-    (void)hipEventRecord(t_prof.ev[3 * t_prof.next + which], stream);
-    if (which == 2) {
-        t_prof.pending = false;
-        t_prof.next = (t_prof.next + 1) % kProfSlots;
-        if (t_prof.count < kProfSlots) ++t_prof.count;
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    if (t_prof.device != dev) {
+        t_prof.destroy();
+        t_prof.device = dev;
     }
+    if (which < 0) {  // a new call begins: drop what a failed call left
+        t_prof.give(t_prof.cur);
+        t_prof.pending = false;
+        return;
+    }
+    if (which == 1 && !t_prof.pending) return;
+    if (which == 2) {
+        if (!t_prof.pending) return;  // a call that launched no pair kernel is not recorded
+        hipEvent_t e = t_prof.take();
+        if (!e) return;
+        (void)hipEventRecord(e, stream);
+        t_prof.cur.end = e;
+        t_prof.calls.push_back(std::move(t_prof.cur));
+        t_prof.cur = ProfCall{};
+        t_prof.pending = false;
+        if (t_prof.calls.size() > kProfCalls) {
+            t_prof.give(t_prof.calls.front());
+            t_prof.calls.pop_front();
+        }
+        return;
+    }
+    hipEvent_t e = t_prof.take();
+    if (!e) return;
+    (void)hipEventRecord(e, stream);
+    t_prof.cur.pair.push_back(e);
+    if (which == 0) t_prof.pending = true;
 }
 
 // ---------------------------------------------------------------- variants
@@ -376,8 +473,7 @@ void record_tuned_variant(int kind, int64_t n, int index)
     write_cache_locked();
 }
 
-// has_v: for the backward, whether potential weights (grad_p) are given.
-static int select_variant(int kind, int64_t n, bool has_v = true)
+int select_variant(int kind, int64_t n, bool has_v)
 {
     int v = forced_variant(kind);
     if (v >= 0) return v;
@@ -396,7 +492,7 @@ using namespace nbody;
 
 // ====================================================================== ABI
 
-static bool bad_eps2(float eps2) { return !(eps2 >= 0.0f) || std::isinf(eps2); }
+bool nbody::bad_eps2(float eps2) { return !(eps2 >= 0.0f) || std::isinf(eps2); }
 
 extern "C" {
 
@@ -452,6 +548,7 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
         const int forced = forced_variant(NBODY_KIND_FORWARD);
         variant = forward_variant_f64sum(forced) ? forced : forward_default_f64sum_variant(n);
     }
+    prof_mark((hipStream_t)stream, -1);
     st = forward_run(variant, dev, x, m, (int)n, eps2, a, p, (hipStream_t)stream);
     if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
     return st;
@@ -480,6 +577,7 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
     Device dev;
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
+    prof_mark((hipStream_t)stream, -1);
     st = backward_run(select_variant(NBODY_KIND_BACKWARD, n, grad_p != nullptr), dev, x, m, (int)n, eps2, grad_a,
                       grad_p, grad_x, grad_m, (hipStream_t)stream);
     if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
@@ -519,6 +617,7 @@ nbody_status nbody_forces_batched(const int64_t *offsets, int64_t num_systems, c
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     const int64_t mean_n = num_systems > 0 ? n / num_systems : 0;
+    prof_mark((hipStream_t)stream, -1);
     st = batched_run(select_variant(NBODY_KIND_BATCHED, mean_n), dev, offsets, num_systems, x,
                      m, eps2, a, p, (hipStream_t)stream);
     if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
@@ -606,6 +705,7 @@ nbody_status nbody_leapfrog(float *x, float *v, float *a, const float *m, int64_
         e.drift = last ? 0 : 1;
         e.xh = (!last && x_hist) ? x_hist + 3 * (size_t)n * (size_t)(t + 1) : nullptr;
         bool fused = false;
+        prof_mark(s, -1);
         st = forward_run(variant, dev, x, m, (int)n, eps2, a, nullptr, s, &e, &fused);
         if (st == NBODY_OK && !fused) st = lf_epilogue_run(a, nullptr, n, e, s);
         if (st == NBODY_OK) prof_mark(s, 2);
@@ -662,6 +762,7 @@ nbody_status nbody_leapfrog_adjoint(const float *pos, const float *m, int64_t n,
         e.c = c;
         e.chain = chain ? 1 : 0;
         bool fused = false;
+        prof_mark(s, -1);
         nbody_status r = backward_run(variant, dev, xp, m, (int)n, eps2, lv, nullptr, gx, gm, s,
                                       &e, &fused);
         if (r == NBODY_OK && !fused) r = lf_epilogue_run(gx, gm, n, e, s);
@@ -681,6 +782,28 @@ nbody_status nbody_leapfrog_adjoint(const float *pos, const float *m, int64_t n,
         st = vjp(pos + stride * (size_t)(t - 1), first ? -half : -dt, t > 1);
     }
     return st;
+}
+
+int64_t nbody_variant_plan(int kind, int index, int64_t n, int num_cu, int blocks_per_cu,
+                           int64_t free_bytes, int *timed)
+{
+    clear_error();
+    if (timed) *timed = 0;
+    int64_t bytes = -1, max_n = -1;
+    if (kind == NBODY_KIND_FORWARD) {
+        bytes = forward_plan_bytes(index, n, num_cu, blocks_per_cu);
+        max_n = forward_variant_max_n(index);
+    } else if (kind == NBODY_KIND_BACKWARD) {
+        bytes = backward_plan_bytes(index, n, num_cu, blocks_per_cu);
+        max_n = backward_variant_max_n(index);
+    }
+    if (bytes < 0 || free_bytes < 0) {
+        fail(NBODY_ERROR_INVALID_ARGUMENT, "no plan for kind %d variant %d at n = %lld", kind, index,
+             (long long)n);
+        return -1;
+    }
+    if (timed) *timed = tune_admissible(n, max_n, bytes, tune_workspace_cap((size_t)free_bytes));
+    return bytes;
 }
 
 int nbody_variant_count(int kind) { return variant_count(kind); }
@@ -741,9 +864,7 @@ nbody_status nbody_profile_enable(int on)
 {
     clear_error();
     g_prof_on.store(on != 0);
-    t_prof.next = 0;
-    t_prof.count = 0;
-    t_prof.pending = false;
+    t_prof.clear();
     return NBODY_OK;
 }
 
@@ -751,24 +872,25 @@ nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls)
 {
     clear_error();
     double sm = 0.0, st = 0.0;
-    const int cnt = t_prof.count;
-    for (int k = 0; k < cnt; ++k) {
-        const int slot = (t_prof.next - cnt + k + kProfSlots) % kProfSlots;
-        hipEvent_t *e = &t_prof.ev[3 * slot];
-        hipError_t err = hipEventSynchronize(e[2]);
+    const size_t cnt = t_prof.calls.size();
+    for (ProfCall &c : t_prof.calls) {
+        hipError_t err = hipEventSynchronize(c.end);
         if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize(profile)");
-        float a = 0.f, b = 0.f;
-        err = hipEventElapsedTime(&a, e[0], e[1]);
-        if (err == hipSuccess) err = hipEventElapsedTime(&b, e[0], e[2]);
+        for (size_t k = 0; k + 1 < c.pair.size(); k += 2) {
+            float a = 0.f;
+            err = hipEventElapsedTime(&a, c.pair[k], c.pair[k + 1]);
+            if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime(profile)");
+            sm += a;
+        }
+        float b = 0.f;
+        err = hipEventElapsedTime(&b, c.pair[0], c.end);
         if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime(profile)");
-        sm += a;
         st += b;
     }
     if (main_ms) *main_ms = cnt ? sm / cnt : 0.0;
     if (total_ms) *total_ms = cnt ? st / cnt : 0.0;
-    if (calls) *calls = cnt;
-    t_prof.next = 0;
-    t_prof.count = 0;
+    if (calls) *calls = (int)cnt;
+    t_prof.clear();
     return NBODY_OK;
 }
 

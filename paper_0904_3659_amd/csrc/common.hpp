@@ -44,6 +44,23 @@ nbody_status workspace_aux(const Device &dev, hipStream_t stream, size_t bytes, 
 // with a kernel when first allocated or grown.
 nbody_status counters(const Device &dev, hipStream_t stream, size_t count, int **ptr);
 
+// Where a call's library workspace comes from: the per-(device, stream)
+// grow-only cache above (base == NULL), or a fixed region of `cap` bytes
+// that the caller owns (the entry point that allocates nothing), with
+// `counter_count` int counters at `counters` that are zero between calls.
+struct Arena {
+    void *base = nullptr;
+    size_t cap = 0;
+    int *counters = nullptr;
+    size_t counter_count = 0;
+    // Bytes a kernel family may plan for, given its own default limit.
+    size_t budget(size_t dflt) const { return base ? (cap < dflt ? cap : dflt) : dflt; }
+    // `bytes` of workspace (INVALID_ARGUMENT if a fixed region is too small).
+    nbody_status get(const Device &dev, hipStream_t stream, size_t bytes, void **ptr) const;
+    // `count` counters that are zero between calls.
+    nbody_status get_counters(const Device &dev, hipStream_t stream, size_t count, int **ptr) const;
+};
+
 // NBODY_FAULT=<what> makes the named step report failure (tests of the
 // error paths; checked on the host before anything is launched).
 bool fault_injected(const char *what);
@@ -58,6 +75,12 @@ nbody_status check_launch(const char *what);
 // Profiling marks (no-ops unless nbody_profile_enable(1)): 0 before the
 // pair kernel, 1 after it, 2 after the call's last kernel (commits).
 void prof_mark(hipStream_t stream, int which);
+
+// Variant of `kind` for size n: forced, else tuned, else the default (for
+// the backward, has_v tells whether potential weights are given).
+int select_variant(int kind, int64_t n, bool has_v = true);
+// eps2 negative, NaN or infinite (rejected by every entry point).
+bool bad_eps2(float eps2);
 
 // Forced variant (>= 0) for a kind, or -1 for automatic choice.
 int forced_variant(int kind);
@@ -77,12 +100,25 @@ int forward_default_f64sum_variant(int64_t n);
 // runs lf_epilogue_run).
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m,
                          int n, float eps2, float *a, float *p, hipStream_t stream,
-                         const LfEpi *epi = nullptr, bool *fused = nullptr);
+                         const LfEpi *epi = nullptr, bool *fused = nullptr,
+                         const Arena &arena = Arena{});
 
 // Pair-once forward kernel (forward_sym.hip) with W waves and K rows/lane.
 nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
                              const float *x, const float *m, int n, float eps2, float *a, float *p,
-                             hipStream_t stream, const LfEpi *epi = nullptr, bool *fused = nullptr);
+                             hipStream_t stream, const LfEpi *epi, bool *fused,
+                             const Arena &arena);
+
+// Occupancy of the pair-once forward kernel with W waves and K rows/lane.
+nbody_status forward_sym_occupancy(int W, int K, int *per_cu);
+// Workspace bytes of a forward variant at size n on a device of num_cu CUs
+// where its pair kernel fits per_cu workgroups per CU (host arithmetic
+// only), or -1 for bad arguments or a size its plan cannot hold.
+int64_t forward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu);
+// Largest n the variant timer times a forward variant at.
+int64_t forward_variant_max_n(int variant);
+// Workgroups per CU of a forward variant's pair kernel.
+nbody_status forward_variant_occupancy(int variant, int *per_cu);
 
 // ---- backward (vector-Jacobian product of Eq. (gravity))
 int backward_variant_count();
@@ -94,7 +130,13 @@ int backward_default_variant(int64_t n, bool has_v);
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m,
                           int n, float eps2, const float *ga, const float *gp,
                           float *gx, float *gm, hipStream_t stream,
-                          const LfEpi *epi = nullptr, bool *fused = nullptr);
+                          const LfEpi *epi = nullptr, bool *fused = nullptr,
+                          const Arena &arena = Arena{});
+
+// As the forward_* planning functions, for the backward variants.
+int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu);
+int64_t backward_variant_max_n(int variant);
+nbody_status backward_variant_occupancy(int variant, int *per_cu);
 
 // ---- batched independent systems
 int batched_variant_count();
@@ -121,6 +163,20 @@ nbody_status fill_synthetic(float *x, float *m, float *w, float *v, int n, uint3
                             hipStream_t stream);
 
 // ---- variant timer (nbody_autotune)
+// The timer times a variant only where its size band admits n and its
+// workspace (-1: its plan cannot hold n) fits `cap`.
+inline bool tune_admissible(int64_t n, int64_t max_n, int64_t ws_bytes, size_t cap)
+{
+    return ws_bytes >= 0 && n <= max_n && (size_t)ws_bytes <= cap;
+}
+// Workspace cap of the timer: NBODY_TUNE_WORKSPACE_CAP bytes (default 2 GiB)
+// or a quarter of the device's free memory, whichever is smaller.
+size_t tune_workspace_cap(size_t free_bytes);
+// Bytes of the (device, stream) workspace, and shrinking it back to at
+// most `bytes` (freed if 0; synchronises when it frees).
+size_t workspace_size(const Device &dev, hipStream_t stream);
+nbody_status workspace_trim(const Device &dev, hipStream_t stream, size_t bytes);
+
 nbody_status autotune_run(int kind, const Device &dev, const int64_t *sizes, int64_t count,
                           hipStream_t stream);
 // Times every batched variant on the caller's ensemble and records the

@@ -26,6 +26,7 @@
 // No atomics: the result is bitwise reproducible for a given variant, n
 // and split count.
 #include "common.hpp"
+#include "pair_once.hpp"
 
 #include <algorithm>
 #include <cstdio>
@@ -339,16 +340,20 @@ struct Variant {
     int sym_w, sym_k, sym_occ;
     LaFn la;  // one-launch split gather (wave-split workgroups x S splits)
     int la_w;
-    bool d64;  // float64 running sums (forward_kernel's D64)
+    bool d64;     // float64 running sums (forward_kernel's D64)
+    bool la_one;  // one-launch kernel with a single split: no partials, no ticket
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0, false}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0, false, false}
 #define FWD_D64_VARIANT(B, K, U)                                                               \
     {"fwd_b" #B "_k" #K "_u" #U "_f64sum", B, K, U, forward_kernel<B, K, U, false, true>,      \
-     forward_kernel<B, K, U, true, true>, 0, 0, 0, nullptr, 0, true}
-#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0, false}
-#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false}
+     forward_kernel<B, K, U, true, true>, 0, 0, 0, nullptr, 0, true, false}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0, false, false}
+#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false, false}
+// The same kernel with one split: the W waves of a row block's workgroup
+// share all of j, and their wave-ordered sum is the result.
+#define FWD_LA1_VARIANT(W) {"fwd_la1_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false, true}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -379,6 +384,8 @@ const Variant kVariants[] = {
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
+    FWD_LA1_VARIANT(8),
+    FWD_LA1_VARIANT(16),
     // float64 running sums, for accuracy at very large n
     FWD_D64_VARIANT(256, 1, 8),
     FWD_D64_VARIANT(64, 1, 8),
@@ -403,9 +410,9 @@ static int variant_index(const char *name)
 }
 
 // Measured on MI355X: the pair-once kernel wins from about 3,000 particles
-// on; its partial buffer grows as 8 n^2 / P bytes (P = 128 to 2048
-// particles per block), so beyond 2^21 particles the gather kernel, which
-// needs no workspace at that size, takes over.
+// on.  Its workspace is bounded (ring groups, about 1 GiB up to 2^22
+// particles, 256 n bytes above); beyond 2^24 particles, where a group would
+// hold very few ring offsets, the float64-sum gather takes over.
 int forward_default_variant(int64_t n)
 {
     // The gather keeps float64 row sums: as fast as float32 sums and
@@ -416,10 +423,9 @@ int forward_default_variant(int64_t n)
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_o1");
     static const int pair_once_1 = variant_index("fwd_sym_w1_k4_o1");
     static const int pair_once_small = variant_index("fwd_sym_w1_k2_o1");
-    if (n > (1 << 21)) return gather_big;
+    if (n > (1 << 24)) return gather_big;
     // 8-wave blocks of 2,048 particles, two workgroups per CU: 1% ahead of
-    // 16-wave blocks at 2^20 (same-box A/B, repeated); their partial
-    // workspace is 8 n^2 / 2048 bytes (4.3 GB at 2^20, 17 GB at 2^21)
+    // 16-wave blocks at 2^20 (same-box A/B, repeated)
     if (n >= (1 << 17)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
     if (n >= 12000) return pair_once_1;
@@ -452,30 +458,98 @@ static int choose_splits(int n, int iblocks, int tile, int num_cu)
     return s;
 }
 
+// Geometry of the one-launch kernel for n rows: j-splits per 64-row block
+// and j per wave.  Waves per row block: about 4096 waves over the chip (4
+// per SIMD), at least 32 j per wave, at most n / 32 waves.
+static void la_geometry(const Variant &V, int n, int num_cu, int *splits_out, int *chunk_out)
+{
+    const int rb = (n + 63) / 64;
+    int per_rb = std::max(1, 4 * 4 * num_cu / rb);
+    per_rb = std::min(per_rb, std::max(1, n / 32));
+    int splits = V.la_one ? 1 : std::max(1, (per_rb + V.la_w / 2) / V.la_w);
+    const int waves = splits * V.la_w;
+    int chunk = (n + waves - 1) / waves;
+    chunk = chunk >= 64 ? (chunk + 63) / 64 * 64 : (chunk + 15) / 16 * 16;
+    splits = std::max(1, (int)(((int64_t)n + (int64_t)chunk * V.la_w - 1) / ((int64_t)chunk * V.la_w)));
+    *splits_out = splits;
+    *chunk_out = chunk;
+}
+
+// Geometry of the row gather: j-splits and j per split (a multiple of the
+// tile).
+static void gather_geometry(const Variant &V, int n, int num_cu, int *splits_out, int *chunk_out)
+{
+    const int iblk = V.block * V.k;
+    const int iblocks = (n + iblk - 1) / iblk;
+    int splits = choose_splits(n, iblocks, V.block, num_cu);
+    int chunk = (n + splits - 1) / splits;
+    chunk = (chunk + V.block - 1) / V.block * V.block;
+    *splits_out = (n + chunk - 1) / chunk;
+    *chunk_out = chunk;
+}
+
+int64_t forward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
+{
+    if (variant < 0 || variant >= kNumVariants || n < 0 || n > NBODY_MAX_N || num_cu < 1 ||
+        per_cu < 1)
+        return -1;
+    if (n == 0) return 0;
+    const Variant &V = kVariants[variant];
+    int splits = 1, chunk = 0;
+    if (V.la_w) {
+        la_geometry(V, (int)n, num_cu, &splits, &chunk);
+        return splits > 1 ? (int64_t)sizeof(float4) * splits * n : 0;
+    }
+    if (V.sym_w) {
+        SymPlan pl;
+        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu, V.sym_occ,
+                      sym_workspace_budget(n), &pl))
+            return -1;
+        return (int64_t)pl.bytes();
+    }
+    gather_geometry(V, (int)n, num_cu, &splits, &chunk);
+    const int64_t entry = V.d64 ? 4 * (int64_t)sizeof(double) : (int64_t)sizeof(float4);
+    return splits > 1 ? entry * splits * n : 0;
+}
+
+int64_t forward_variant_max_n(int variant)
+{
+    if (variant < 0 || variant >= kNumVariants) return -1;
+    // the one-launch kernels are built for launch-latency-bound sizes
+    return kVariants[variant].la_w ? (1 << 16) : NBODY_MAX_N;
+}
+
+nbody_status forward_variant_occupancy(int variant, int *per_cu)
+{
+    const Variant &V = kVariants[variant];
+    hipError_t e;
+    if (V.sym_w) return forward_sym_occupancy(V.sym_w, V.sym_k, per_cu);
+    if (V.la_w)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.la, V.la_w * 64, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.partial, V.block, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (*per_cu < 1) *per_cu = 1;
+    return NBODY_OK;
+}
+
 nbody_status forward_run(int variant, const Device &dev, const float *x, const float *m, int n,
                          float eps2, float *a, float *p, hipStream_t stream, const LfEpi *epi,
-                         bool *fused)
+                         bool *fused, const Arena &arena)
 {
     const Variant &V = kVariants[variant];
     if (fused) *fused = false;
     if (V.la_w) {
-        // Waves per row block: about 4096 waves over the chip (4 per SIMD),
-        // at least 32 j per wave, at most n / 32 waves.
         const int rb = (n + 63) / 64;
-        int per_rb = std::max(1, 4 * 4 * dev.num_cu / rb);
-        per_rb = std::min(per_rb, std::max(1, n / 32));
-        int splits = std::max(1, (per_rb + V.la_w / 2) / V.la_w);
-        const int waves = splits * V.la_w;
-        int chunk = (n + waves - 1) / waves;
-        chunk = chunk >= 64 ? (chunk + 63) / 64 * 64 : (chunk + 15) / 16 * 16;
-        splits = std::max(1, (int)(((int64_t)n + (int64_t)chunk * V.la_w - 1) / ((int64_t)chunk * V.la_w)));
+        int splits = 1, chunk = 0;
+        la_geometry(V, n, dev.num_cu, &splits, &chunk);
         LaArgs P{x, m, n, eps2, chunk, splits, nullptr, nullptr, a, p};
         if (splits > 1) {
             void *ws = nullptr;
-            nbody_status st = workspace(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
+            nbody_status st = arena.get(dev, stream, sizeof(float4) * (size_t)splits * n, &ws);
             if (st != NBODY_OK) return st;
             P.partial = static_cast<float4 *>(ws);
-            st = counters(dev, stream, (size_t)rb, &P.ctr);
+            st = arena.get_counters(dev, stream, (size_t)rb, &P.ctr);
             if (st != NBODY_OK) return st;
         }
         if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
@@ -486,13 +560,11 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
     }
     if (V.sym_w)
         return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream,
-                               epi, fused);
+                               epi, fused, arena);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
-    int splits = choose_splits(n, iblocks, V.block, dev.num_cu);
-    int chunk = (n + splits - 1) / splits;
-    chunk = (chunk + V.block - 1) / V.block * V.block;
-    splits = (n + chunk - 1) / chunk;
+    int splits = 1, chunk = 0;
+    gather_geometry(V, n, dev.num_cu, &splits, &chunk);
 
     FwdArgs P{x, m, n, eps2, chunk, nullptr, a, p, nullptr};
     if (splits == 1) {
@@ -504,7 +576,7 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
     }
     void *ws = nullptr;
     const size_t entry = V.d64 ? 4 * sizeof(double) : sizeof(float4);
-    nbody_status st = workspace(dev, stream, entry * (size_t)splits * n, &ws);
+    nbody_status st = arena.get(dev, stream, entry * (size_t)splits * n, &ws);
     if (st != NBODY_OK) return st;
     if (V.d64)
         P.partial_d = static_cast<double *>(ws);

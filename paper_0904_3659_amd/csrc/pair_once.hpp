@@ -35,11 +35,17 @@
 // serialise and were 4x slower).  After the 64 steps the W waves' slot
 // pairs are added in wave order and written as the tile's partial.
 //
-// Partials (float4 per particle, [C + M/2][n]): slots 0..C-1 hold the i-side
-// sums of the C chunks; slot C+delta-1 holds what particle j in block J
-// received from block J - delta.  A second pass adds, per particle, its
-// slots in fixed order.  No atomics, no cross-workgroup races: the result is
-// bitwise reproducible for a given variant, n and chunk count.
+// Ring groups and partials.  The ring offsets are processed in groups of
+// consecutive deltas, one launch per group, so that library memory stays
+// O((C + G) n) instead of O(n^2 / P): launch g covers deltas [d_lo, d_hi)
+// (the first group also the diagonal, delta 0) and writes float4 partials
+// [C + G][n]: slots 0..C-1 hold the i-side sums of the C chunks over the
+// group's tiles, slot C + delta - max(d_lo, 1) holds what particle j in
+// block J received from block J - delta.  A fold kernel then adds each
+// particle's slots of the group, in fixed order and in float64, to its
+// running sum (the last group's fold rounds it and stores a, p).  No
+// atomics, no cross-workgroup races: the result is bitwise reproducible for
+// a given variant, n, chunk count and group size.
 //
 // Padding: rows past n take position +1e18 and mass 0, tile slots past n
 // take -1e18 and mass 0, so padded terms are exactly zero for finite
@@ -47,6 +53,8 @@
 #pragma once
 
 #include "common.hpp"
+
+#include <cstdlib>
 
 namespace nbody {
 
@@ -69,74 +77,181 @@ __host__ __device__ __forceinline__ int ring_in(int J, int M)
     return (M - 1) / 2 + (((M & 1) == 0 && J >= M / 2) ? 1 : 0);
 }
 
-// Final sum of the pair-once kernels: particle j's output is the sum of its
-// C chunk slots and the ring_in(J, M) j-side slots its block J received
-// (partial[k][j], k < C + ring_in).  Four groups of 64 threads each add a
-// contiguous quarter of the slots in slot order, and the four group sums are
-// added in group order: a fixed order (bitwise reproducible) with four times
-// the parallelism of one thread per particle.  xyz goes to out3[j][3], w to
-// out1[j] (skipped when out1 is NULL).  A workgroup covers 64 particles.
-// With EPI the leap-frog update `e` follows the store (leapfrog_epi.hpp).
+// The deltas of group [d_lo, d_hi) that have a j-side slot (the diagonal,
+// delta 0, has none): [max(d_lo, 1), d_hi).
+__host__ __device__ __forceinline__ int group_first_delta(int d_lo) { return d_lo > 0 ? d_lo : 1; }
+
+// Fold of one ring group: particle j (block J) adds its C chunk slots and
+// the j-side slots of the group's deltas its block received, deltas
+// [dj, min(d_hi, ring_in(J, M) + 1)), in slot order, each widened to
+// float64.  Four groups of 64 threads each add a contiguous quarter of the
+// slots, and the four group sums are added in group order; the group's sum
+// is then added to the particle's running sum acc (FIRST: acc is not read;
+// LAST: the result is rounded once and xyz goes to out3[j][3], w to out1[j],
+// skipped when out1 is NULL, followed by the leap-frog update `e` with EPI).
+// A fixed order throughout: bitwise reproducible.  A workgroup covers 64
+// particles.  acc is [n] double4 and is neither read nor written when the
+// fold is both FIRST and LAST.
 template <int PB, bool EPI = false>
-__global__ __launch_bounds__(256) void slot_reduce_kernel(const float4 *__restrict__ partial,
-                                                          int n, int M, int C, float *out3,
-                                                          float *out1, LfEpi e)
+__global__ __launch_bounds__(256) void slot_fold_kernel(const float4 *__restrict__ partial, int n,
+                                                        int M, int C, int d_lo, int d_hi,
+                                                        int first, int last, double4 *acc,
+                                                        float *out3, float *out1, LfEpi e)
 {
-    __shared__ float4 red[4][64];
+    __shared__ double4 red[4][64];
     const int l = threadIdx.x & 63;
     const int g = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + l;
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
     if (j < n) {
-        const int S = C + ring_in(j / PB, M);
+        const int dj = group_first_delta(d_lo);
+        const int recv = min(d_hi, ring_in(j / PB, M) + 1) - dj;
+        const int S = C + (recv > 0 ? recv : 0);
         const int q = (S + 3) / 4;
         const int k1 = min(S, (g + 1) * q);
 #pragma unroll 4
         for (int k = g * q; k < k1; ++k) {
             const float4 v = partial[(size_t)k * n + j];
-            s.x += v.x;
-            s.y += v.y;
-            s.z += v.z;
-            s.w += v.w;
+            s.x += (double)v.x;
+            s.y += (double)v.y;
+            s.z += (double)v.z;
+            s.w += (double)v.w;
         }
     }
     red[g][l] = s;
     __syncthreads();
     if (g != 0 || j >= n) return;
-    float4 t = red[0][l];
+    double4 t = red[0][l];
 #pragma unroll
     for (int g2 = 1; g2 < 4; ++g2) {
-        const float4 v = red[g2][l];
+        const double4 v = red[g2][l];
         t.x += v.x;
         t.y += v.y;
         t.z += v.z;
         t.w += v.w;
     }
+    if (!first) {
+        const double4 r = acc[j];
+        t.x += r.x;
+        t.y += r.y;
+        t.z += r.z;
+        t.w += r.w;
+    }
+    if (!last) {
+        acc[j] = t;
+        return;
+    }
+    const float4 f = make_float4((float)t.x, (float)t.y, (float)t.z, (float)t.w);
     if constexpr (EPI) {
-        lf_finish(e, j, t, out3, out1);
+        lf_finish(e, j, f, out3, out1);
     } else {
-        out3[3 * j + 0] = t.x;
-        out3[3 * j + 1] = t.y;
-        out3[3 * j + 2] = t.z;
-        if (out1) out1[j] = t.w;
+        out3[3 * j + 0] = f.x;
+        out3[3 * j + 1] = f.y;
+        out3[3 * j + 2] = f.z;
+        if (out1) out1[j] = f.w;
     }
 }
 
-// Tile u of block I's sequence: the TPB diagonal tiles (delta 0), then the
-// ring tiles delta-major.  Returns the first particle index of the tile.
+// Launch plan of a single-system pair-once evaluation: M blocks of P
+// particles, C chunks per block, D = M/2 ring deltas processed in `groups`
+// launches of G deltas each (the first also the diagonal).  Workspace:
+// partials [C + G][n] float4 and, with more than one group, a float64
+// running sum [n] double4.
+struct SymPlan {
+    int M = 0, C = 0, G = 0, groups = 0;
+    size_t partial_bytes = 0, acc_bytes = 0;
+    size_t bytes() const { return partial_bytes + acc_bytes; }
+};
+
+// Plan for n particles in blocks of P, given the number of workgroups the
+// device holds at once (resident; the chunk count fills them, divided by
+// occ) and a workspace budget in bytes.  Returns false if even one delta
+// per group and one chunk per block exceed the budget.
+inline bool sym_plan(int64_t n, int P, int64_t resident, int occ, size_t budget, SymPlan *out)
+{
+    SymPlan pl;
+    const int TPB = P / 64;
+    pl.M = (int)((n + P - 1) / P);
+    const int D = pl.M / 2;  // ring deltas 1..D
+    int64_t C = resident / ((int64_t)pl.M * occ);
+    const int64_t max_c = (int64_t)(D + 1) * TPB;  // tiles of a block's sequence
+    C = C < 1 ? 1 : (C > max_c ? max_c : C);
+    const size_t slot = 16 * (size_t)n;          // one float4 per particle
+    const int64_t slots = (int64_t)(budget / slot);
+    if (C + D <= slots || D == 0) {
+        pl.C = (int)C;
+        pl.G = D;
+        pl.groups = 1;
+    } else {
+        // several groups: room for C + G slots plus the running sum (two
+        // slots' worth); the chunks take at most half of the slots
+        if (slots < 4) return false;
+        const int64_t half = (slots - 2) / 2;
+        if (C > half) C = half;
+        const int64_t gmax = slots - C - 2;
+        pl.groups = (int)((D + gmax - 1) / gmax);
+        pl.G = (D + pl.groups - 1) / pl.groups;
+        const int64_t cg = (int64_t)pl.G * TPB;  // tiles per block in a later group
+        pl.C = (int)(C > cg ? cg : C);
+    }
+    pl.partial_bytes = slot * (size_t)(pl.C + pl.G);
+    pl.acc_bytes = pl.groups > 1 ? 32 * (size_t)n : 0;
+    *out = pl;
+    return true;
+}
+
+// Ring deltas [d_lo, d_hi) of group g of a plan (delta 0, the diagonal, is
+// in group 0).
+inline void sym_group(const SymPlan &pl, int g, int *d_lo, int *d_hi)
+{
+    *d_lo = g == 0 ? 0 : 1 + g * pl.G;
+    const int hi = 1 + (g + 1) * pl.G;
+    *d_hi = hi < pl.M / 2 + 1 ? hi : pl.M / 2 + 1;
+}
+
+// Library workspace allowed for one pair-once evaluation of n particles
+// (partials and running sum) before the ring is split into more groups:
+// 1 GiB, or 16 float4 slots per particle where that is more (n > 2^22).
+// The environment variable NBODY_SYM_WORKSPACE=<bytes> sets another limit
+// (tests use it to split small rings into many groups).
+inline size_t sym_workspace_budget(int64_t n)
+{
+    if (const char *env = std::getenv("NBODY_SYM_WORKSPACE")) {
+        const unsigned long long v = std::strtoull(env, nullptr, 10);
+        if (v > 0) return (size_t)v;
+    }
+    const size_t slots16 = 256 * (size_t)n;
+    return slots16 > ((size_t)1 << 30) ? slots16 : ((size_t)1 << 30);
+}
+
+// Number of tiles of block I in ring group [d_lo, d_hi): the TPB diagonal
+// tiles when d_lo == 0, then TPB tiles per ring delta the block meets.
+__host__ __device__ __forceinline__ int group_tiles(int I, int M, int d_lo, int d_hi, int TPB)
+{
+    const int dj = group_first_delta(d_lo);
+    const int hi = min(d_hi - 1, ring_len(I, M));
+    return (d_lo == 0 ? TPB : 0) + (hi >= dj ? (hi - dj + 1) * TPB : 0);
+}
+
+// Tile u of block I's sequence in ring group [d_lo, ...): the TPB diagonal
+// tiles (delta 0) when the group holds them, then the ring tiles
+// delta-major.  Returns the first particle index of the tile.
 template <int PB>
-__device__ __forceinline__ int tile_base(int u, int I, int M, int &delta)
+__device__ __forceinline__ int tile_base(int u, int I, int M, int d_lo, int &delta)
 {
     constexpr int TPB = PB / 64;
-    if (u < TPB) {
-        delta = 0;
-        return I * PB + u * 64;
+    if (d_lo == 0) {
+        if (u < TPB) {
+            delta = 0;
+            return I * PB + u * 64;
+        }
+        u -= TPB;
     }
-    const int q = u - TPB;
-    delta = 1 + q / TPB;
+    const int q = u / TPB;
+    delta = group_first_delta(d_lo) + q;
     int J = I + delta;
     if (J >= M) J -= M;
-    return J * PB + (q - (delta - 1) * TPB) * 64;
+    return J * PB + (u - q * TPB) * 64;
 }
 
 __device__ __forceinline__ float4 load_particle(const float *__restrict__ x,
@@ -404,8 +519,9 @@ __device__ __forceinline__ void tile_steps(const float (&xi)[K], const float (&y
 template <int W, int K, bool SKIP_PAD = false, bool POT = true>
 __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                                                 const float *__restrict__ m, int n, float eps2,
-                                                int M, int I, int c, int C, float4 *partial,
-                                                float4 *tile, float4 (*jacc)[kSlotLds])
+                                                int M, int I, int c, int C, int d_lo, int d_hi,
+                                                float4 *partial, float4 *tile,
+                                                float4 (*jacc)[kSlotLds])
 {
     constexpr int PB = W * 64 * K;   // particles per block
     constexpr int TPB = PB / 64;     // 64-particle tiles per block
@@ -436,9 +552,10 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     // row groups of this wave that hold particles (K except in a last block)
     const int kv = SKIP_PAD ? min(K, max(0, (n - (I * PB + wv * 64 * K) + 63) / 64)) : K;
 
-    // ---- this chunk's share of the block's tile sequence; tiles that hold
-    // only padding are skipped (uniform).
-    const int U = TPB + ring_len(I, M) * TPB;
+    // ---- this chunk's share of the block's tile sequence in the group;
+    // tiles that hold only padding are skipped (uniform).
+    const int U = group_tiles(I, M, d_lo, d_hi, TPB);
+    const int dj = group_first_delta(d_lo);
     const int u0 = (int)((long long)U * c / C);
     const int u1 = (int)((long long)U * (c + 1) / C);
     // Small workgroups prefetch the next tile into registers while the
@@ -458,7 +575,7 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
     constexpr bool kSelfDiag = (W == 1);
     int u = u0, delta = 0, jbase = 0;
     for (; u < u1; ++u)
-        if ((jbase = tile_base<PB>(u, I, M, delta)) < n) break;
+        if ((jbase = tile_base<PB>(u, I, M, d_lo, delta)) < n) break;
     float4 next = make_float4(0.f, 0.f, 0.f, 0.f);
     if (kPrefetch && u < u1 && tid < 64) next = load_particle(x, m, jbase + tid, n);
 
@@ -476,7 +593,7 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
         __syncthreads();
         const int cur_u = u, cur_delta = delta, cur_base = jbase;
         for (++u; u < u1; ++u)
-            if ((jbase = tile_base<PB>(u, I, M, delta)) < n) break;
+            if ((jbase = tile_base<PB>(u, I, M, d_lo, delta)) < n) break;
         if (kPrefetch && u < u1 && tid < 64) next = load_particle(x, m, jbase + tid, n);
 
         float tx[K], ty[K], tz[K], tp[K];
@@ -533,7 +650,7 @@ __device__ __forceinline__ void pair_once_block(const float *__restrict__ x,
                     sum.w += v.w;
                 }
                 const int j = cur_base + tid;
-                if (j < n) partial[(size_t)(C + cur_delta - 1) * n + j] = sum;
+                if (j < n) partial[(size_t)(C + cur_delta - dj) * n + j] = sum;
             }
         } else if (kOnceDiag && wv == t / K) {
             // this wave holds diagonal tile t's rows (lane-slot t % K); the

@@ -20,7 +20,7 @@ import torch
 from . import build as _build
 
 FORWARD, BACKWARD, BATCHED = 0, 1, 2
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 _STATUS = {
     0: "NBODY_OK",
@@ -77,9 +77,13 @@ def lib() -> ctypes.CDLL:
         L.nbody_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int)]
+        L.nbody_variant_plan.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int,
+                                         ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_int)]
+        L.nbody_variant_plan.restype = _i64
         L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
         L.nbody_selected_variant.restype = ctypes.c_int
-        for f in ("nbody_forces", "nbody_forces_ex", "nbody_forces_backward", "nbody_forces_batched",
+        for f in ("nbody_forces", "nbody_forces_ex",
+                  "nbody_forces_backward", "nbody_forces_batched",
                   "nbody_axpy",
                   "nbody_kick_drift", "nbody_leapfrog", "nbody_leapfrog_adjoint",
                   "nbody_set_variant", "nbody_autotune", "nbody_autotune_batched",
@@ -374,6 +378,18 @@ def autotune_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float) -> 
                                             _ptr(x), _ptr(m), _eps2(eps2), _stream(x.device)))
     systems = o.size - 1
     return selected_variant(BATCHED, n // systems if systems > 0 else 0)
+
+
+def variant_plan(kind: int, index: int, n: int, num_cu: int, blocks_per_cu: int,
+                 free_bytes: int) -> tuple[int, bool]:
+    """(workspace bytes, timed by the variant timer) of a variant at size n,
+    from host arithmetic only (``nbody_variant_plan``)."""
+    timed = ctypes.c_int(0)
+    b = lib().nbody_variant_plan(kind, index, n, num_cu, blocks_per_cu, free_bytes,
+                                 ctypes.byref(timed))
+    if b < 0:
+        raise NBodyError(1, lib().nbody_last_error().decode())
+    return int(b), bool(timed.value)
 
 
 def release_workspace() -> None:

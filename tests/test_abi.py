@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.nbody_abi_version() == 3
+    assert L.nbody_abi_version() == 4
     for code, name in enumerate(["NBODY_OK", "NBODY_ERROR_INVALID_ARGUMENT",
                                  "NBODY_ERROR_UNSUPPORTED_DEVICE", "NBODY_ERROR_OUT_OF_MEMORY",
                                  "NBODY_ERROR_LAUNCH_FAILED", "NBODY_ERROR_INTERNAL"]):

@@ -138,3 +138,36 @@ def test_ensemble_timer_keeps_a_captured_plan():
                          text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert json.loads(out.stdout.strip().splitlines()[-1])["same"] == [True, True, True]
+
+
+CHILD_BIG = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_0904_3659_amd import nbody as nb
+dev = torch.device("cuda", 0)
+torch.cuda.synchronize()
+free0, total = torch.cuda.mem_get_info(dev)
+nb.autotune(nb.FORWARD, [1 << 20])
+torch.cuda.synchronize()
+free1, _ = torch.cuda.mem_get_info(dev)
+print(json.dumps({"free0": free0, "free1": free1,
+                  "chosen": nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, 1 << 20)]}))
+"""
+
+
+def test_autotune_at_a_million_keeps_workspace_under_the_cap(tmp_path):
+    # Every variant the gate admits at 2^20 is timed (the one-launch kernels
+    # are outside their size band); the timer gives back the workspace it
+    # grew, so the device's free memory afterwards is within the timer's
+    # cap (2 GiB) of what it was before.
+    need_gpu()
+    env = dict(os.environ, NBODY_TUNE_CACHE=str(tmp_path / "tune.json"))
+    out = subprocess.run([sys.executable, "-c", CHILD_BIG, ROOT], env=env, capture_output=True,
+                         text=True, timeout=280)
+    assert out.returncode == 0, out.stderr[-2000:]
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    print(f"[autotune 2^20] chose {r['chosen']}, free before {r['free0']} after {r['free1']}",
+          flush=True)
+    assert r["free0"] - r["free1"] <= 2 << 30
+    assert not r["chosen"].startswith("fwd_la")

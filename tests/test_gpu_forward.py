@@ -227,7 +227,10 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 1 << 20)].startswith("fwd_sym")
     assert names[nb.selected_variant(nb.FORWARD, 65536)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_sym")
-    assert not names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
+    # the pair-once workspace is bounded (ring groups): default up to 2^24
+    assert names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
+    assert names[nb.selected_variant(nb.FORWARD, 1 << 24)].startswith("fwd_sym")
+    assert not names[nb.selected_variant(nb.FORWARD, (1 << 24) + 1)].startswith("fwd_sym")
     # one-launch split gather: no reduction launch for small n
     assert names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_la")
 
@@ -276,30 +279,76 @@ def test_one_launch_split_gather(nb, n):
         nb.set_variant(nb.FORWARD, -1)
 
 
-def test_f64_sum_at_four_million(nb):
-    # float64 row sums remove the growth of the float32 error with the number
-    # of j-tiles: at n = 2^22 the float32-sum gather errs ~1e-5 and the
-    # float64-sum one ~1e-7 (the pair terms themselves stay float32)
+def test_four_million(nb):
+    # n = 2^22: the default pair-once kernel runs its ring in groups of
+    # offsets (bounded workspace) with float64 running sums between groups;
+    # the float32-sum gather errs ~1e-5 here and the float64-sum one ~1e-7
+    # (the pair terms themselves stay float32 in all three)
     dev = need_gpu()
     w = inputs.plummer_4m_lognormal()
     ar, pr = R.forces_rows(w.x, w.m, w.eps2, w.rows)
     x, m = to_dev(w.x, dev), to_dev(w.m, dev)
     names = nb.variant_names(nb.FORWARD)
+    assert names[nb.selected_variant(nb.FORWARD, w.n)].startswith("fwd_sym")
     try:
         nb.set_variant(nb.FORWARD, names.index("fwd_b64_k1_u8"))
         a32, p32 = nb.forces(x, m, w.eps2)
         nb.set_variant(nb.FORWARD, -1)
         a64, p64 = nb.forces(x, m, w.eps2, f64_sum=True)
-        assert names[nb.selected_variant(nb.FORWARD, w.n)].endswith("_f64sum")
         a_def, p_def = nb.forces(x, m, w.eps2)
-        assert torch.equal(a_def, a64) and torch.equal(p_def, p64)
+        a_def2, p_def2 = nb.forces(x, m, w.eps2)
+        assert torch.equal(a_def, a_def2) and torch.equal(p_def, p_def2)
     finally:
         nb.set_variant(nb.FORWARD, -1)
     e32 = errors(host(a32)[w.rows], host(p32)[w.rows], ar, pr)
     e64 = errors(host(a64)[w.rows], host(p64)[w.rows], ar, pr)
-    print(f"[parity] {w.name} float32 sums {e32}  float64 sums {e64}", flush=True)
+    e_def = errors(host(a_def)[w.rows], host(p_def)[w.rows], ar, pr)
+    print(f"[parity] {w.name} float32-sum gather {e32}  float64-sum gather {e64}  "
+          f"pair-once default {e_def}", flush=True)
     assert max(e64) <= 1e-6
     assert max(e64) * 10 <= max(e32)
+    assert max(e_def) <= 1e-4
+
+
+def test_above_a_million_default(nb):
+    # 2^20 + 4,099 bodies, ragged: the default pair-once kernel with its
+    # ring in several groups, on 4,096 oracle rows
+    dev = need_gpu()
+    n = (1 << 20) + 4099
+    x = inputs.plummer_positions(n, (67, 0))
+    m = inputs.lognormal_masses(n, (67, 1))
+    rows = inputs.check_rows(n, 4096, (67, 2))
+    assert nb.variant_names(nb.FORWARD)[nb.selected_variant(nb.FORWARD, n)].startswith("fwd_sym")
+    a, p = _run(nb, x, m, 1e-6, dev)
+    ar, pr = R.forces_rows(x, m, 1e-6, rows)
+    assert_parity(a[rows], p[rows], ar, pr, label=f"default n={n} (4096 rows)")
+
+
+@pytest.mark.parametrize("n", [4097, 2048 * 5 + 17, 20000])
+def test_ring_groups(nb, n, monkeypatch):
+    # a small workspace limit splits the ring into many launches (one to a
+    # few offsets each); every split meets the oracle, is bitwise
+    # repeatable, and with the potential dropped gives the same a
+    dev = need_gpu()
+    x = inputs.plummer_positions(n, (68, n))
+    m = inputs.lognormal_masses(n, (68, n, 1))
+    ar, pr = R.forces(x, m, 1e-4)
+    xd, md = to_dev(x, dev), to_dev(m, dev)
+    names = nb.variant_names(nb.FORWARD)
+    try:
+        for name in ("fwd_sym_w1_k2_o1", "fwd_sym_w4_k4_o1", "fwd_sym_w8_k4_o1"):
+            nb.set_variant(nb.FORWARD, names.index(name))
+            for slots in (5, 7, 12):
+                monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * slots))
+                print(f"[ring groups] {name} n={n} budget {slots} slots", flush=True)
+                a1, p1 = nb.forces(xd, md, 1e-4)
+                a2, p2 = nb.forces(xd, md, 1e-4)
+                a3, _ = nb.forces(xd, md, 1e-4, potential=False)
+                torch.cuda.synchronize()
+                assert torch.equal(a1, a2) and torch.equal(p1, p2) and torch.equal(a1, a3)
+                assert_parity(host(a1), host(p1), ar, pr, label=f"{name} n={n} {slots} slots")
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
 
 
 @pytest.mark.parametrize("n", [20000, 70000])

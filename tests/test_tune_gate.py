@@ -1,0 +1,107 @@
+"""The variant timer's gate and the pair-once workspace bound, on the CPU:
+nbody_variant_plan computes a variant's launch plan from its arguments
+alone (no device), with the same functions the library launches with."""
+
+import ctypes
+import os
+
+import pytest
+
+from paper_0904_3659_amd import build as B
+
+GiB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIBRARY):
+        pytest.skip("libnbody.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(B.LIBRARY)
+    lib.nbody_variant_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]
+    lib.nbody_variant_plan.restype = ctypes.c_int64
+    lib.nbody_variant_name.restype = ctypes.c_char_p
+    return lib
+
+
+def names(L, kind):
+    return [L.nbody_variant_name(kind, k).decode() for k in range(L.nbody_variant_count(kind))]
+
+
+def plan(L, kind, name, n, per_cu, free=256 * GiB, num_cu=256):
+    timed = ctypes.c_int(-1)
+    b = L.nbody_variant_plan(kind, names(L, kind).index(name), n, num_cu, per_cu, free,
+                             ctypes.byref(timed))
+    return b, timed.value
+
+
+def test_pair_once_workspace_closed_form(L):
+    # 2^20 bodies in 512 blocks of 2,048, two workgroups per CU on 256 CUs:
+    # one chunk per block; 256 ring offsets; a 1 GiB budget holds 64 slots
+    # of 16 MiB, so 5 groups of 52 offsets: (1 + 52) slots plus the float64
+    # running sum (32 bytes per body)
+    n = 1 << 20
+    b, _ = plan(L, 0, "fwd_sym_w8_k4_o1", n, 2)
+    assert b == 53 * 16 * n + 32 * n
+    # small n: the whole ring in one launch, no running sum: chunks fill the
+    # 2 x 256 resident workgroups (M = 8 blocks -> 64 chunks, capped at the
+    # 5 x 32 tiles of a block's sequence), plus 4 ring slots
+    n = 16384
+    b, _ = plan(L, 0, "fwd_sym_w8_k4_o1", n, 2)
+    assert b == (64 + 4) * 16 * n
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("n", [1 << 20, (1 << 21) + 5, 1 << 22])
+def test_pair_once_workspace_bounded(L, kind, n):
+    # the quadratic workspace (8 n^2 / P) is gone: at most 1 GiB up to 2^22
+    # for every pair-once variant and occupancy
+    prefix = ("fwd_sym", "bwd_sym")[kind]
+    for name in [v for v in names(L, kind) if v.startswith(prefix)]:
+        for per_cu in (1, 2, 8, 32):
+            b, timed = plan(L, kind, name, n, per_cu)
+            assert 0 < b <= GiB, (name, per_cu, b)
+            assert timed == 1, (name, per_cu)
+
+
+def test_gate_size_band_and_cap(L):
+    fwd = names(L, 0)
+    n = 1 << 20
+    # the one-launch kernels are not timed beyond their size band
+    for name in [v for v in fwd if v.startswith("fwd_la")]:
+        b, timed = plan(L, 0, name, n, 4)
+        assert b >= 0 and timed == 0, name
+        assert plan(L, 0, name, 1 << 14, 4)[1] == 1, name
+    # with 1 GiB free the cap is 256 MiB: the pair-once kernels (about
+    # 0.9 GiB here) are skipped, the gathers (no workspace at this size)
+    # are timed
+    for name in fwd:
+        b, timed = plan(L, 0, name, n, 2, free=GiB)
+        if name.startswith("fwd_sym"):
+            assert b > GiB // 4 and timed == 0, name
+        elif name.startswith("fwd_b"):
+            assert b <= GiB // 4 and timed == 1, name
+    # the cap is a quarter of free memory: 0.86 GiB fits with 4 GiB free,
+    # not with 3 GiB
+    b, timed = plan(L, 0, "fwd_sym_w8_k4_o1", n, 2, free=4 * GiB)
+    assert b == 53 * 16 * n + 32 * n and timed == 1
+    assert plan(L, 0, "fwd_sym_w8_k4_o1", n, 2, free=3 * GiB)[1] == 0
+
+
+def test_gate_cap_from_environment(L, monkeypatch):
+    # NBODY_TUNE_WORKSPACE_CAP lowers the 2 GiB ceiling
+    n = 1 << 20
+    assert plan(L, 0, "fwd_sym_w8_k4_o1", n, 2)[1] == 1
+    monkeypatch.setenv("NBODY_TUNE_WORKSPACE_CAP", str(512 << 20))
+    assert plan(L, 0, "fwd_sym_w8_k4_o1", n, 2)[1] == 0
+    assert plan(L, 0, "fwd_b64_k1_u8", n, 2)[1] == 1
+
+
+def test_bad_arguments(L):
+    t = ctypes.c_int(7)
+    assert L.nbody_variant_plan(2, 0, 1000, 256, 2, GiB, ctypes.byref(t)) == -1 and t.value == 0
+    assert L.nbody_variant_plan(0, 10 ** 6, 1000, 256, 2, GiB, None) == -1
+    assert L.nbody_variant_plan(0, 0, -1, 256, 2, GiB, None) == -1
+    assert L.nbody_variant_plan(0, 0, 1000, 0, 2, GiB, None) == -1
+    assert L.nbody_variant_plan(1, 0, 1000, 256, 0, GiB, None) == -1
+    assert L.nbody_variant_plan(0, 0, 0, 256, 2, GiB, None) == 0
