@@ -119,6 +119,32 @@ const char *nbody_last_error(void);
 nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
                           float *a, float *p, void *stream);
 
+/* Bytes of device memory behind nbody_forces_noalloc, per device. */
+#define NBODY_NOALLOC_SCRATCH_BYTES (INT64_C(64) << 20)
+
+/*
+ * nbody_forces for callers that cannot allocate device memory: code under
+ * HIP graph capture, serving loops that must not call hipMalloc, harnesses
+ * that forbid it.  Same sum, arguments, layouts, ownership, variant choice
+ * and errors as nbody_forces, and bitwise its result whenever that call's
+ * workspace would fit the region below; the call itself allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).
+ *
+ * Its workspace is a fixed region of NBODY_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * of device memory that the library holds on every device it runs on until
+ * the process ends (its last 4 KiB are int counters, zeroed by a fill
+ * kernel on `stream` at the first call on a device).  The pair-once kernels
+ * split their ring into more launches to fit it, which bounds n at about
+ * 2^20 particles; a call whose kernels cannot fit the region returns
+ * INVALID_ARGUMENT with the sizes in nbody_last_error().
+ * Every call on one device shares that device's region and leaves the last
+ * call's partial sums in it: calls that overlap in time on one device (two
+ * streams, two host threads) race and give undefined results.  Serialise
+ * them, or use nbody_forces.
+ */
+nbody_status nbody_forces_noalloc(const float *x, const float *m, int64_t n, float eps2,
+                                  float *a, float *p, void *stream);
+
 /* Flag bits of nbody_forces_ex. */
 #define NBODY_FORCES_F64_SUM 1u
 

@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_last_error.restype = ctypes.c_char_p
         L.nbody_forces.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp]
         L.nbody_forces_ex.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, ctypes.c_uint32, _vp]
+        L.nbody_forces_noalloc.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp]
         L.nbody_forces_backward.argtypes = [_vp, _vp, _i64, _f32, _vp, _vp, _vp, _vp, _vp]
         L.nbody_forces_batched.argtypes = [ctypes.POINTER(_i64), _i64, _vp, _vp, _f32, _vp, _vp, _vp]
         L.nbody_axpy.argtypes = [_vp, _vp, _i64, _f32, _vp]
@@ -82,7 +83,7 @@ def lib() -> ctypes.CDLL:
         L.nbody_variant_plan.restype = _i64
         L.nbody_selected_variant.argtypes = [ctypes.c_int, _i64]
         L.nbody_selected_variant.restype = ctypes.c_int
-        for f in ("nbody_forces", "nbody_forces_ex",
+        for f in ("nbody_forces", "nbody_forces_ex", "nbody_forces_noalloc",
                   "nbody_forces_backward", "nbody_forces_batched",
                   "nbody_axpy",
                   "nbody_kick_drift", "nbody_leapfrog", "nbody_leapfrog_adjoint",
@@ -178,6 +179,25 @@ def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential
         else:
             _check(lib().nbody_forces(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p),
                                       _stream(dev)))
+    return a, p
+
+
+def forces_noalloc(x: torch.Tensor, m: torch.Tensor, eps2: float, a: torch.Tensor,
+                   p: torch.Tensor | None = None):
+    """:func:`forces` through ``nbody_forces_noalloc``: the library
+    allocates nothing for the call (its workspace is a fixed 64 MiB device
+    region per device).  The caller supplies the outputs ``a`` [n,3] and,
+    optionally, ``p`` [n]; calls that overlap in time on one device race."""
+    n = int(x.shape[0]) if x.dim() == 2 else -1
+    _want(x, "x", (n, 3))
+    dev = x.device
+    _want(m, "m", (n,), dev)
+    _want(a, "a", (n, 3), dev)
+    if p is not None:
+        _want(p, "p", (n,), dev)
+    with _on(dev):
+        _check(lib().nbody_forces_noalloc(_ptr(x), _ptr(m), n, _eps2(eps2), _ptr(a), _ptr(p),
+                                          _stream(dev)))
     return a, p
 
 

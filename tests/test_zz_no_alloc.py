@@ -1,0 +1,72 @@
+"""nbody_forces_noalloc (the forward with its workspace in the library's
+fixed device region) against nbody_forces, through the C ABI."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import reference as R
+from paper_0904_3659_amd import inputs
+from tests.gpu_util import assert_parity, host, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    need_gpu()
+    from paper_0904_3659_amd import nbody
+    return nbody
+
+
+def _pair(nb, n, key, dev):
+    x = to_dev(inputs.plummer_positions(n, (80, key)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (80, key, 1)), dev)
+    a_ref, p_ref = nb.forces(x, m, 1e-4)
+    a = torch.full((n, 3), float("nan"), device=dev)
+    p = torch.full((n,), float("nan"), device=dev)
+    nb.forces_noalloc(x, m, 1e-4, a, p)
+    torch.cuda.synchronize()
+    return x, m, a, p, a_ref, p_ref
+
+
+@pytest.mark.parametrize("sizes", [(20000, 1024), (9000, 333), (4097, 3001)])
+def test_two_calls_in_a_row_match_nbody_forces(nb, sizes):
+    # two calls in a row, the second smaller: the region keeps the first
+    # call's partial sums, which must not leak into the second result
+    dev = need_gpu()
+    for k, n in enumerate(sizes):
+        print(f"[noalloc] n={n}", flush=True)
+        x, m, a, p, a_ref, p_ref = _pair(nb, n, k, dev)
+        # same kernels and plan when the default workspace fits the region
+        assert torch.equal(a, a_ref) and torch.equal(p, p_ref), n
+        rows = np.arange(0, n, max(1, n // 512))
+        ar, pr = R.forces_rows(host(x), host(m), 1e-4, rows)
+        assert_parity(host(a)[rows], host(p)[rows], ar, pr, label=f"noalloc n={n}")
+
+
+def test_ring_split_to_fit_the_region(nb):
+    # 2^18 bodies: the default plan needs more than the region, so the
+    # pair-once ring runs in more launches; results within the tolerance
+    dev = need_gpu()
+    n = (1 << 18) + 77
+    print(f"[noalloc] n={n}", flush=True)
+    x, m, a, p, a_ref, p_ref = _pair(nb, n, 9, dev)
+    rows = inputs.check_rows(n, 1024, (80, 9, 2))
+    ar, pr = R.forces_rows(host(x), host(m), 1e-4, rows)
+    assert_parity(host(a)[rows], host(p)[rows], ar, pr, label=f"noalloc n={n}")
+    assert_parity(host(a_ref)[rows], host(p_ref)[rows], ar, pr, label=f"nbody_forces n={n}")
+    # then a small call again, bitwise that of nbody_forces
+    x, m, a, p, a_ref, p_ref = _pair(nb, 3001, 10, dev)
+    assert torch.equal(a, a_ref) and torch.equal(p, p_ref)
+
+
+def test_too_large_is_refused(nb):
+    dev = need_gpu()
+    n = 1 << 22
+    x = torch.zeros((n, 3), device=dev)
+    m = torch.zeros((n,), device=dev)
+    a = torch.empty((n, 3), device=dev)
+    with pytest.raises(nb.NBodyError) as ei:
+        nb.forces_noalloc(x, m, 1e-4, a)
+    assert ei.value.status == 1 and "workspace" in str(ei.value)
