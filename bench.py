@@ -207,9 +207,10 @@ def timed_calls(fn, reps: int, torch, nb, events_in_timed_loop: bool = False):
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
-    main_ms, total_ms, calls = nb.profile_read()
+    main_ms, total_ms, calls, launches = nb.profile_read(launches=True)
     nb.profile_enable(False)
     assert calls == reps, (calls, reps)
+    timed_calls.launches = launches
     return wall, main_ms, total_ms
 
 
@@ -578,6 +579,7 @@ def main() -> int:
     log(f"forward timed x{args.steps}")
     with SclkSampler(torch, dev) as clk:
         wall, kern_ms, call_ms = timed_calls(fwd, args.steps, torch, nb, events_in_timed_loop=True)
+    launches = timed_calls.launches
     # host copy of the last timed result, checked against the oracle below
     a_last = a.cpu().numpy().astype(np.float64)
     p_last = p.cpu().numpy().astype(np.float64)
@@ -610,6 +612,10 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": variant, "kernel_ms": kern_ms, "call_kernels_ms": call_ms,
+                     # the pair kernel runs as several launches (ring groups):
+                     # kernel_ms is their sum per evaluation
+                     "kernel_launches_per_call": launches,
+                     "kernel_ms_per_launch": kern_ms / launches if launches else None,
                      "flop_per_pair": metrics.FLOP_PER_PAIR,
                      "evaluated_pairs": evaluated,
                      # FP32 operations the hardware counted for this kernel

@@ -390,12 +390,13 @@ nbody_status nbody_profile_enable(int on);
 
 /*
  * Wait for the recorded calls of this thread and return the mean over them
- * of the summed durations of a call's pair kernels (main_ms) and of the time
- * from its first pair kernel's start to its last kernel's end (total_ms),
- * and their number (calls; 0 leaves the means at 0).  Clears the record.
- * NULL outputs are skipped.
+ * of the summed durations of a call's pair kernels (main_ms), of the time
+ * from its first pair kernel's start to its last kernel's end (total_ms)
+ * and of the number of pair kernels a call launched (launches), and their
+ * number (calls; 0 leaves the means at 0).  Clears the record.  NULL
+ * outputs are skipped.
  */
-nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls);
+nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls, double *launches);
 
 #ifdef __cplusplus
 }

@@ -868,12 +868,13 @@ nbody_status nbody_profile_enable(int on)
     return NBODY_OK;
 }
 
-nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls)
+nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls, double *launches)
 {
     clear_error();
-    double sm = 0.0, st = 0.0;
+    double sm = 0.0, st = 0.0, nl = 0.0;
     const size_t cnt = t_prof.calls.size();
     for (ProfCall &c : t_prof.calls) {
+        nl += (double)(c.pair.size() / 2);
         hipError_t err = hipEventSynchronize(c.end);
         if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize(profile)");
         for (size_t k = 0; k + 1 < c.pair.size(); k += 2) {
@@ -890,6 +891,7 @@ nbody_status nbody_profile_read(double *main_ms, double *total_ms, int *calls)
     if (main_ms) *main_ms = cnt ? sm / cnt : 0.0;
     if (total_ms) *total_ms = cnt ? st / cnt : 0.0;
     if (calls) *calls = (int)cnt;
+    if (launches) *launches = cnt ? nl / cnt : 0.0;
     t_prof.clear();
     return NBODY_OK;
 }

@@ -77,7 +77,8 @@ def lib() -> ctypes.CDLL:
         L.nbody_profile_enable.argtypes = [ctypes.c_int]
         L.nbody_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double),
-                                         ctypes.POINTER(ctypes.c_int)]
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]
         L.nbody_variant_plan.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int,
                                          ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_int)]
         L.nbody_variant_plan.restype = _i64
@@ -421,11 +422,13 @@ def profile_enable(on: bool = True) -> None:
     _check(lib().nbody_profile_enable(1 if on else 0))
 
 
-def profile_read():
-    """(mean pair-kernel ms, mean whole-call ms, calls) since the last read."""
-    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
-    _check(lib().nbody_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+def profile_read(launches: bool = False):
+    """(mean summed pair-kernel ms, mean whole-call ms, calls) since the last
+    read; with ``launches`` also the mean number of pair kernels per call."""
+    a, b, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().nbody_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                    ctypes.byref(d)))
+    return (a.value, b.value, c.value, d.value) if launches else (a.value, b.value, c.value)
 
 
 def __getattr__(name):
