@@ -175,3 +175,49 @@ def test_no_potential_weights_kernel(nb, n):
     finally:
         nb.set_variant(nb.BACKWARD, -1)
     assert torch.equal(gx0, gx2) and torch.equal(gm0, gm2)
+
+
+@pytest.mark.parametrize("n", [4097, 10257])
+def test_every_pair_once_variant_without_potential_weights(nb, n):
+    # Each pair-once adjoint, forced: without potential weights (grad_p
+    # NULL, the kernel that skips their terms) it must equal the same
+    # variant with explicit zero weights bitwise, and meet the oracle.  The
+    # leap-frog adjoint runs these kernels.
+    dev = need_gpu()
+    x, m, w, _ = _system(n, 60 + n)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, None)
+    xd, md, wd = to_dev(x, dev), to_dev(m, dev), to_dev(w, dev)
+    zero = torch.zeros((n,), device=dev)
+    names = nb.variant_names(nb.BACKWARD)
+    try:
+        for name in [nm for nm in names if nm.startswith("bwd_sym")]:
+            print(f"[adjoint sweep] {name} n={n}", flush=True)
+            nb.set_variant(nb.BACKWARD, names.index(name))
+            gx0, gm0 = nb.forces_backward(xd, md, 1e-3, wd, zero)
+            gx1, gm1 = nb.forces_backward(xd, md, 1e-3, wd, None)
+            torch.cuda.synchronize()
+            assert torch.equal(gx0, gx1) and torch.equal(gm0, gm1), name
+            _check(host(gx1), host(gm1), rx, rm, f"{name} n={n} no v")
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+
+
+@pytest.mark.parametrize("n", [4097, 20000])
+def test_adjoint_ring_groups(nb, n, monkeypatch):
+    # the adjoint's ring split into many launches by a small workspace
+    # limit: the oracle still holds and the result repeats bitwise
+    dev = need_gpu()
+    x, m, w, v = _system(n, 70 + n)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    names = nb.variant_names(nb.BACKWARD)
+    try:
+        for name in ("bwd_sym_w1_k2_o1", "bwd_sym_w2_k2_o1", "bwd_sym_w8_k2_o1"):
+            nb.set_variant(nb.BACKWARD, names.index(name))
+            for slots in (5, 9):
+                monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * slots))
+                g1 = _grad(nb, x, m, 1e-3, w, v, dev)
+                g2 = _grad(nb, x, m, 1e-3, w, v, dev)
+                assert np.array_equal(g1[0], g2[0]) and np.array_equal(g1[1], g2[1])
+                _check(g1[0], g1[1], rx, rm, f"{name} n={n} {slots} slots")
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)

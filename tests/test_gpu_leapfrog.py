@@ -298,3 +298,41 @@ def test_paper_experiment2_standins_against_fp64_integrator(nb, k):
     print(f"[parity] {name}: x {e_x:.2e} (tol {tol_x:.2e}), v {e_v:.2e} (tol {tol_v:.2e}); "
           f"FP64 spread x {s_x:.2e} v {s_v:.2e}", flush=True)
     assert e_x <= tol_x and e_v <= tol_v
+
+
+@pytest.mark.parametrize("n", [9000, 20001])
+def test_leapfrog_calls_with_ring_groups(nb, n, monkeypatch):
+    # A small workspace limit splits the pair-once ring into many launches;
+    # the leap-frog update then runs in the epilogue of the last group's
+    # fold.  Device-resident steps and their reverse sweep must still equal
+    # the composed calls bitwise, and the trajectory must meet the FP64
+    # integrator.
+    dev = need_gpu()
+    monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * 7))
+    x, v, m, u = _case(n, 9)
+    xt, vt, mt = to_dev(x, dev), to_dev(v, dev), to_dev(m, dev)
+    eps2, dt, steps = 1e-4, 1e-3, 4
+    print(f"[leapfrog ring groups] n={n}", flush=True)
+    a0, _ = nb.forces(xt, mt, eps2, potential=False)
+    x1, v1, a1 = xt.clone(), vt.clone(), a0.clone()
+    pos = torch.empty((steps + 1, n, 3), device=dev)
+    pos[0].copy_(xt)
+    nb.leapfrog_(x1, v1, a1, mt, eps2, dt, steps, x_hist=pos[1:])
+    x2, v2, a2 = xt.clone(), vt.clone(), a0.clone()
+    ref = _composed_forward(nb, x2, v2, a2, mt, eps2, dt, steps)
+    torch.cuda.synchronize()
+    assert all(torch.equal(p, q) for p, q in zip((x1, v1, a1), (x2, v2, a2)))
+    for t in range(steps):
+        assert torch.equal(pos[t + 1], ref[t])
+    rx, rv = R.leapfrog(x, v, m, eps2, dt, steps)
+    assert np.abs(host(x1) - rx).max() <= 1e-5 * np.abs(rx).max()
+    lx0 = to_dev(u, dev)
+    lv0 = to_dev(inputs.normal((n, 3), (70, 9, 4)), dev)
+    lm0 = to_dev(inputs.normal((n,), (70, 9, 5)), dev)
+    got = [t.clone() for t in (lx0, lv0, lm0)]
+    nb.leapfrog_adjoint_(pos, mt, eps2, dt, *got, flags=3)
+    want = [t.clone() for t in (lx0, lv0, lm0)]
+    _composed_adjoint(nb, pos, mt, eps2, dt, *want, 3)
+    torch.cuda.synchronize()
+    for g, r in zip(got, want):
+        assert torch.equal(g, r)
