@@ -127,8 +127,11 @@ nbody_status nbody_forces(const float *x, const float *m, int64_t n, float eps2,
  * HIP graph capture, serving loops that must not call hipMalloc, harnesses
  * that forbid it.  Same sum, arguments, layouts, ownership, variant choice
  * and errors as nbody_forces, and bitwise its result whenever that call's
- * workspace would fit the region below; the call itself allocates nothing
- * (no hipMalloc, hipFree or allocating library routine).
+ * workspace would fit the region below (or NBODY_SYM_WORKSPACE holds
+ * nbody_forces to the region's NBODY_NOALLOC_SCRATCH_BYTES - 4096 bytes);
+ * where it would not, the ring runs in more launches and the two results
+ * differ in rounding only.  The call itself allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).
  *
  * Its workspace is a fixed region of NBODY_NOALLOC_SCRATCH_BYTES (64 MiB)
  * of device memory that the library holds on every device it runs on until

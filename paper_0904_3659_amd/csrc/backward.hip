@@ -587,8 +587,9 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         if (kk[k] < n) A.partial[(size_t)c * n + kk[k]] = acc[k];
 }
 
-// OCC divides the chunk count (as in the pair-once forward kernel).
-template <int W, int K, int OCC>
+// OCC divides the chunk count and ROUNDS multiplies it (as in the
+// pair-once forward kernel).
+template <int W, int K, int OCC, int ROUNDS = 1>
 nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
                               int n, float eps2, const float *ga, const float *gp, float *gx,
                               float *gm, hipStream_t stream, const LfEpi *epi, bool *fused,
@@ -601,7 +602,8 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     SymPlan pl;
-    if (!sym_plan(n, PB, (int64_t)per_cu * dev.num_cu, OCC, arena.budget(sym_workspace_budget(n)), &pl))
+    if (!sym_plan(n, PB, (int64_t)per_cu * dev.num_cu * ROUNDS, OCC,
+                  arena.budget(sym_workspace_budget(n)), &pl))
         return fail(NBODY_ERROR_INVALID_ARGUMENT,
                     "n = %d needs more than the %zu-byte workspace limit of %s", n,
                     arena.budget(sym_workspace_budget(n)), name);
@@ -658,14 +660,18 @@ struct Variant {
     KernelFn direct, partial;
     SymRunFn sym;
     SymKernelFn sym_kernel;
-    int sym_w, sym_k, sym_occ;
+    int sym_w, sym_k, sym_occ, sym_rounds;
 };
 
 #define BWD_VARIANT(B, K, U) \
-    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr, nullptr, 0, 0, 0}
+    {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr, nullptr, 0, 0, 0, 1}
 #define BWD_SYM_VARIANT(W, K, O) \
     {"bwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, O>, \
-     backward_sym_kernel<W, K, true>, W, K, O}
+     backward_sym_kernel<W, K, true>, W, K, O, 1}
+// Pair-once blocks in R rounds of workgroups (R times the chunks).
+#define BWD_SYM_R_VARIANT(W, K, R) \
+    {"bwd_sym_w" #W "_k" #K "_r" #R, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, 1, R>, \
+     backward_sym_kernel<W, K, true>, W, K, 1, R}
 
 const Variant kVariants[] = {
     BWD_VARIANT(256, 2, 4),
@@ -686,6 +692,9 @@ const Variant kVariants[] = {
     BWD_SYM_VARIANT(1, 2, 1),
     BWD_SYM_VARIANT(2, 1, 1),
     BWD_SYM_VARIANT(1, 4, 1),
+    BWD_SYM_R_VARIANT(1, 2, 8),
+    BWD_SYM_R_VARIANT(2, 2, 8),
+    BWD_SYM_R_VARIANT(2, 1, 8),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -716,13 +725,21 @@ int backward_default_variant(int64_t n, bool has_v)
 {
     static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
     static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
-    static const int pair_once_nov = variant_index("bwd_sym_w1_k2_o1");
+    static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
+    static const int pair_once_nov_small = variant_index("bwd_sym_w2_k1_r8");
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int gather_small = variant_index("bwd_b128_k1_u8");
     if (n > (1 << 24)) return gather;
-    if (!has_v && n >= 6000 && n < (1 << 17)) return pair_once_nov;
+    // eight rounds of one-wave workgroups (down to one tile each, which the
+    // dispatcher hands out as slots free up): 4-9% faster than one round
+    // without potential weights from 9,000 to 2^17 bodies and 3-5% with them
+    // from 10,000 to 24,575 (interleaved A/B); 16% for two-wave one-row
+    // blocks at 6,000 without them
+    if (!has_v && n >= 9000 && n < (1 << 17)) return pair_once_r8;
+    if (!has_v && n >= 6000 && n < 9000) return pair_once_nov_small;
     if (n >= (1 << 16)) return pair_once;
+    if (has_v && n >= 10000 && n < 24576) return pair_once_r8;
     if (has_v && n >= 14000) return pair_once_mid;
     if (n >= (1 << 11)) return pair_once_small;
     return gather_small;
@@ -753,7 +770,7 @@ int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
     const Variant &V = kVariants[variant];
     if (V.sym) {
         SymPlan pl;
-        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu, V.sym_occ,
+        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu * V.sym_rounds, V.sym_occ,
                       sym_workspace_budget(n), &pl))
             return -1;
         return (int64_t)pl.bytes();

@@ -104,9 +104,9 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
                          const Arena &arena = Arena{});
 
 // Pair-once forward kernel (forward_sym.hip) with W waves and K rows/lane.
-nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
-                             const float *x, const float *m, int n, float eps2, float *a, float *p,
-                             hipStream_t stream, const LfEpi *epi, bool *fused,
+nbody_status forward_sym_run(int W, int K, int occ, int rounds, const char *name,
+                             const Device &dev, const float *x, const float *m, int n, float eps2,
+                             float *a, float *p, hipStream_t stream, const LfEpi *epi, bool *fused,
                              const Arena &arena);
 
 // Occupancy of the pair-once forward kernel with W waves and K rows/lane.

@@ -337,7 +337,7 @@ struct Variant {
     const char *name;
     int block, k, unroll;
     KernelFn direct, partial;
-    int sym_w, sym_k, sym_occ;
+    int sym_w, sym_k, sym_occ, sym_rounds;
     LaFn la;  // one-launch split gather (wave-split workgroups x S splits)
     int la_w;
     bool d64;     // float64 running sums (forward_kernel's D64)
@@ -345,15 +345,17 @@ struct Variant {
 };
 
 #define FWD_VARIANT(B, K, U) \
-    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, nullptr, 0, false, false}
+    {"fwd_b" #B "_k" #K "_u" #U, B, K, U, forward_kernel<B, K, U, false>, forward_kernel<B, K, U, true>, 0, 0, 0, 1, nullptr, 0, false, false}
 #define FWD_D64_VARIANT(B, K, U)                                                               \
     {"fwd_b" #B "_k" #K "_u" #U "_f64sum", B, K, U, forward_kernel<B, K, U, false, true>,      \
-     forward_kernel<B, K, U, true, true>, 0, 0, 0, nullptr, 0, true, false}
-#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, nullptr, 0, false, false}
-#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false, false}
+     forward_kernel<B, K, U, true, true>, 0, 0, 0, 1, nullptr, 0, true, false}
+#define FWD_SYM_VARIANT(W, K, O) {"fwd_sym_w" #W "_k" #K "_o" #O, 0, 0, 0, nullptr, nullptr, W, K, O, 1, nullptr, 0, false, false}
+// Pair-once blocks in R rounds of workgroups (R times the chunks).
+#define FWD_SYM_R_VARIANT(W, K, R) {"fwd_sym_w" #W "_k" #K "_r" #R, 0, 0, 0, nullptr, nullptr, W, K, 1, R, nullptr, 0, false, false}
+#define FWD_LA_VARIANT(W) {"fwd_la_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, 1, forward_la_kernel<W>, W, false, false}
 // The same kernel with one split: the W waves of a row block's workgroup
 // share all of j, and their wave-ordered sum is the result.
-#define FWD_LA1_VARIANT(W) {"fwd_la1_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, forward_la_kernel<W>, W, false, true}
+#define FWD_LA1_VARIANT(W) {"fwd_la1_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, 1, forward_la_kernel<W>, W, false, true}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -381,6 +383,9 @@ const Variant kVariants[] = {
     FWD_SYM_VARIANT(1, 2, 1),
     FWD_SYM_VARIANT(2, 2, 1),
     FWD_SYM_VARIANT(4, 2, 1),
+    FWD_SYM_R_VARIANT(1, 4, 8),
+    FWD_SYM_R_VARIANT(1, 2, 8),
+    FWD_SYM_R_VARIANT(4, 4, 8),
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
@@ -420,15 +425,21 @@ int forward_default_variant(int64_t n)
     static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
     static const int one_launch = variant_index("fwd_la_w16");
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
-    static const int pair_once_4 = variant_index("fwd_sym_w4_k4_o1");
-    static const int pair_once_1 = variant_index("fwd_sym_w1_k4_o1");
+    static const int pair_once_4 = variant_index("fwd_sym_w4_k4_r8");
+    static const int pair_once_1 = variant_index("fwd_sym_w1_k4_r8");
+    static const int pair_once_1s = variant_index("fwd_sym_w1_k2_r8");
     static const int pair_once_small = variant_index("fwd_sym_w1_k2_o1");
     if (n > (1 << 24)) return gather_big;
     // 8-wave blocks of 2,048 particles, two workgroups per CU: 1% ahead of
     // 16-wave blocks at 2^20 (same-box A/B, repeated)
     if (n >= (1 << 17)) return pair_once_8;
+    // Below 2^17 a single round of workgroups holds only a few tiles each;
+    // eight rounds of shorter ones (down to one tile) let the dispatcher
+    // even out the tail: 2-8% faster from 16,384 to 65,536 bodies
+    // (interleaved A/B in one process)
     if (n >= (1 << 16)) return pair_once_4;
-    if (n >= 12000) return pair_once_1;
+    if (n >= 24576) return pair_once_1;
+    if (n >= 12000) return pair_once_1s;
     // one-wave blocks of 128 particles: twice the workgroups of 256-particle
     // blocks, which evens out the one round of workgroups these sizes fill
     // (3-17% faster from 3,000 to 10,000 bodies, slower from about 12,000)
@@ -502,7 +513,7 @@ int64_t forward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
     }
     if (V.sym_w) {
         SymPlan pl;
-        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu, V.sym_occ,
+        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu * V.sym_rounds, V.sym_occ,
                       sym_workspace_budget(n), &pl))
             return -1;
         return (int64_t)pl.bytes();
@@ -559,8 +570,8 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
         return check_launch(V.name);
     }
     if (V.sym_w)
-        return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.name, dev, x, m, n, eps2, a, p, stream,
-                               epi, fused, arena);
+        return forward_sym_run(V.sym_w, V.sym_k, V.sym_occ, V.sym_rounds, V.name, dev, x, m, n, eps2,
+                               a, p, stream, epi, fused, arena);
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     int splits = 1, chunk = 0;

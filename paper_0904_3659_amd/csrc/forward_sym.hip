@@ -31,8 +31,11 @@ __global__ __launch_bounds__(W * 64) void forward_sym_kernel(SymArgs A)
 
 // OCC divides the chunk count: 1 fills every resident workgroup slot once;
 // 2 gives half as many, twice as long workgroups (fewer partial slots, less
-// tail imbalance at small n, lower occupancy).
-template <int W, int K, int OCC>
+// tail imbalance at small n, lower occupancy).  ROUNDS multiplies it: that
+// many rounds of shorter workgroups (down to one tile each), which the
+// hardware dispatcher hands out as slots free up, evening out the tail of
+// a grid whose workgroups hold only a few tiles.
+template <int W, int K, int OCC, int ROUNDS = 1>
 nbody_status run_sym(const char *name, const Device &dev, const float *x, const float *m, int n,
                      float eps2, float *a, float *p, hipStream_t stream, const LfEpi *epi,
                      bool *fused, const Arena &arena)
@@ -46,7 +49,8 @@ nbody_status run_sym(const char *name, const Device &dev, const float *x, const 
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     SymPlan pl;
-    if (!sym_plan(n, PB, (int64_t)per_cu * dev.num_cu, OCC, arena.budget(sym_workspace_budget(n)), &pl))
+    if (!sym_plan(n, PB, (int64_t)per_cu * dev.num_cu * ROUNDS, OCC,
+                  arena.budget(sym_workspace_budget(n)), &pl))
         return fail(NBODY_ERROR_INVALID_ARGUMENT,
                     "n = %d needs more than the %zu-byte workspace limit of %s", n,
                     arena.budget(sym_workspace_budget(n)), name);
@@ -114,10 +118,17 @@ nbody_status forward_sym_occupancy(int W, int K, int *per_cu)
     return fail(NBODY_ERROR_INTERNAL, "no pair-once forward kernel for W=%d K=%d", W, K);
 }
 
-nbody_status forward_sym_run(int W, int K, int occ, const char *name, const Device &dev,
-                             const float *x, const float *m, int n, float eps2, float *a, float *p,
-                             hipStream_t stream, const LfEpi *epi, bool *fused, const Arena &arena)
+nbody_status forward_sym_run(int W, int K, int occ, int rounds, const char *name,
+                             const Device &dev, const float *x, const float *m, int n, float eps2,
+                             float *a, float *p, hipStream_t stream, const LfEpi *epi, bool *fused,
+                             const Arena &arena)
 {
+    if (rounds == 8) {
+        if (W == 1 && K == 4 && occ == 1) return run_sym<1, 4, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
+        if (W == 1 && K == 2 && occ == 1) return run_sym<1, 2, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
+        if (W == 4 && K == 4 && occ == 1) return run_sym<4, 4, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
+        return fail(NBODY_ERROR_INTERNAL, "no pair-once forward kernel for W=%d K=%d occ=%d rounds=%d", W, K, occ, rounds);
+    }
     if (W == 8 && K == 4 && occ == 1) return run_sym<8, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
     if (W == 8 && K == 4 && occ == 2) return run_sym<8, 4, 2>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
     if (W == 4 && K == 8 && occ == 1) return run_sym<4, 8, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);

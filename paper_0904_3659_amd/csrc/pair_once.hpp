@@ -194,7 +194,8 @@ inline bool sym_plan(int64_t n, int P, int64_t resident, int occ, size_t budget,
         const int64_t cg = (int64_t)pl.G * TPB;  // tiles per block in a later group
         pl.C = (int)(C > cg ? cg : C);
     }
-    pl.partial_bytes = slot * (size_t)(pl.C + pl.G);
+    // the running sum starts on a 256-byte boundary (double4 needs 32)
+    pl.partial_bytes = (slot * (size_t)(pl.C + pl.G) + 255) / 256 * 256;
     pl.acc_bytes = pl.groups > 1 ? 32 * (size_t)n : 0;
     *out = pl;
     return true;

@@ -30,19 +30,38 @@ def _pair(nb, n, key, dev):
     return x, m, a, p, a_ref, p_ref
 
 
-@pytest.mark.parametrize("sizes", [(20000, 1024), (9000, 333), (4097, 3001)])
-def test_two_calls_in_a_row_match_nbody_forces(nb, sizes):
-    # two calls in a row, the second smaller: the region keeps the first
-    # call's partial sums, which must not leak into the second result
+# Workspace the fixed region offers (its last 4 KiB hold counters).
+REGION = (64 << 20) - 4096
+
+
+@pytest.mark.parametrize("sizes", [(20000, 1024), (9000, 333), (4097, 3001), (70001, 5003)])
+def test_two_calls_in_a_row_match_nbody_forces(nb, sizes, monkeypatch):
+    # Two calls in a row, the second smaller: the region keeps the first
+    # call's partial sums, which must not leak into the second result.
+    # With nbody_forces held to the same workspace limit both calls plan
+    # the same launches, so the results must agree bitwise; both meet the
+    # oracle.
     dev = need_gpu()
+    monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(REGION))
     for k, n in enumerate(sizes):
         print(f"[noalloc] n={n}", flush=True)
         x, m, a, p, a_ref, p_ref = _pair(nb, n, k, dev)
-        # same kernels and plan when the default workspace fits the region
         assert torch.equal(a, a_ref) and torch.equal(p, p_ref), n
         rows = np.arange(0, n, max(1, n // 512))
         ar, pr = R.forces_rows(host(x), host(m), 1e-4, rows)
         assert_parity(host(a)[rows], host(p)[rows], ar, pr, label=f"noalloc n={n}")
+
+
+@pytest.mark.parametrize("n", [20000, 70001])
+def test_default_limit_differs_only_in_rounding(nb, n):
+    # Without that limit nbody_forces may plan one launch where the region
+    # needs several: the two results then differ in rounding only
+    dev = need_gpu()
+    x, m, a, p, a_ref, p_ref = _pair(nb, n, 11, dev)
+    rows = np.arange(0, n, max(1, n // 512))
+    ar, pr = R.forces_rows(host(x), host(m), 1e-4, rows)
+    assert_parity(host(a)[rows], host(p)[rows], ar, pr, label=f"noalloc n={n}")
+    assert_parity(host(a_ref)[rows], host(p_ref)[rows], ar, pr, label=f"nbody_forces n={n}")
 
 
 def test_ring_split_to_fit_the_region(nb):
@@ -56,7 +75,8 @@ def test_ring_split_to_fit_the_region(nb):
     ar, pr = R.forces_rows(host(x), host(m), 1e-4, rows)
     assert_parity(host(a)[rows], host(p)[rows], ar, pr, label=f"noalloc n={n}")
     assert_parity(host(a_ref)[rows], host(p_ref)[rows], ar, pr, label=f"nbody_forces n={n}")
-    # then a small call again, bitwise that of nbody_forces
+    # then a small call again, bitwise that of nbody_forces (its default
+    # workspace fits the region at this size)
     x, m, a, p, a_ref, p_ref = _pair(nb, 3001, 10, dev)
     assert torch.equal(a, a_ref) and torch.equal(p, p_ref)
 
