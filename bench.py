@@ -14,7 +14,7 @@ cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-forward]
        python bench.py --size-sweep               (pairs/s against N instead of the legs)
-       python bench.py --only-leg adjoint|batched (one leg alone, for profiling its kernel)
+       python bench.py --only-leg adjoint|batched|latency (one leg alone, for profiling its kernel)
 """
 
 from __future__ import annotations
@@ -302,12 +302,13 @@ def oracle_checks(held: dict) -> dict:
                 ar, pr = R.forces_rows(w.x, w.m, w.eps2, rows)
                 checks[name] = rel_errors(a[rows], p[rows], ar, pr)
                 checks[name]["rows"] = int(rows.size)
-    if "adjoint" in held:
-        wa, gx, gm = held["adjoint"]
-        rx, rm = R.forces_vjp(wa.x, wa.m, wa.eps2, wa.extra["w"], wa.extra["v"])
-        ex = float(np.abs(gx - rx).max() / np.abs(rx).max())
-        em = float(np.abs(gm - rm).max() / np.abs(rm).max())
-        checks[wa.name] = {"grad_x_normwise": ex, "grad_m_normwise": em, "max": max(ex, em)}
+    for key in ("adjoint", "adjoint_1k"):
+        if key in held:
+            wa, gx, gm = held[key]
+            rx, rm = R.forces_vjp(wa.x, wa.m, wa.eps2, wa.extra["w"], wa.extra["v"])
+            ex = float(np.abs(gx - rx).max() / np.abs(rx).max())
+            em = float(np.abs(gm - rm).max() / np.abs(rm).max())
+            checks[wa.name] = {"grad_x_normwise": ex, "grad_m_normwise": em, "max": max(ex, em)}
     if "batched" in held:
         ens, a, p = held["batched"]
         sizes = ens.sizes()
@@ -440,6 +441,37 @@ def adjoint_leg(nb, torch, dev, inputs, metrics, peak, held=None):
     return wa, rec
 
 
+def latency_leg(nb, torch, dev, inputs, held=None, reps: int = 2000):
+    """Forward and adjoint at N = 1,024, where a call costs launch latency:
+    microseconds per call from Python over `reps` back-to-back calls with
+    preallocated outputs, and the pair kernel's own duration from the
+    library's events.  With ``held`` the adjoint's result is kept for the
+    oracle check."""
+    log("latency leg (N = 1,024)")
+    w = inputs.adjoint_16k(1024)
+    x = torch.from_numpy(w.x).to(dev)
+    m = torch.from_numpy(w.m).to(dev)
+    ga = torch.from_numpy(w.extra["w"]).to(dev)
+    gp = torch.from_numpy(w.extra["v"]).to(dev)
+    a, p = torch.empty_like(x), torch.empty_like(m)
+    gx, gm = torch.empty_like(x), torch.empty_like(m)
+    rec = {"workload": w.name}
+    for kind, fn, k in (("forward", lambda: nb.forces(x, m, w.eps2, out=(a, p)), nb.FORWARD),
+                        ("adjoint", lambda: nb.forces_backward(x, m, w.eps2, ga, gp, out=(gx, gm)),
+                         nb.BACKWARD)):
+        warm_up(fn, torch)
+        wall, km, cm = timed_calls(fn, reps, torch, nb)
+        rec[kind] = {"us_per_call": wall * 1e6 / reps, "pair_kernel_us": km * 1e3,
+                     "kernels_us": cm * 1e3,
+                     "variant": nb.variant_names(k)[nb.selected_variant(k, w.n)]}
+        log(f"{kind} N = 1,024: {wall * 1e6 / reps:.2f} us per call, kernel {km * 1e3:.2f} us")
+    if held is not None:
+        torch.cuda.synchronize()
+        held["adjoint_1k"] = (w, gx.cpu().numpy().astype(np.float64),
+                              gm.cpu().numpy().astype(np.float64))
+    return rec
+
+
 def batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons: bool = True, held=None):
     """The 4,096-system ensemble in one persistent launch, tuned on the
     ensemble first; with ``comparisons`` also the plain per-system launches
@@ -520,7 +552,7 @@ def main() -> int:
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the legs, time the paper's three unrolling programs and "
                          "the default variant over a range of N (pairs/s vs N)")
-    ap.add_argument("--only-leg", choices=("adjoint", "batched"),
+    ap.add_argument("--only-leg", choices=("adjoint", "batched", "latency"),
                     help="run only this leg and print its record (for profiling its kernel; "
                          "the batched leg then skips the tuner and the per-system launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -550,6 +582,8 @@ def main() -> int:
         peak = metrics.MI355X_FP32_VECTOR_TFLOPS
         if args.only_leg == "adjoint":
             rec = adjoint_leg(nb, torch, dev, inputs, metrics, peak)[1]
+        elif args.only_leg == "latency":
+            rec = latency_leg(nb, torch, dev, inputs)
         else:
             rec = batched_leg(nb, torch, dev, inputs, metrics, peak, comparisons=False)
         print(json.dumps({args.only_leg: rec}), flush=True)
@@ -659,6 +693,8 @@ def main() -> int:
                                       ps.cpu().numpy().astype(np.float64))
             log(f"forward {ws.name}: {wl * 1e3 / reps:.4f} ms/call")
         out["forward_other_sizes"] = sizes
+        # ------------------------------------------ latency, forward + adjoint
+        out["latency_n1024"] = latency_leg(nb, torch, dev, inputs, held)
 
     if not args.only_forward:
         # ------------------------------------------------------ adjoint, 16k

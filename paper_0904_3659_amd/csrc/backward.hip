@@ -17,6 +17,7 @@
 // the running sums (two-level accumulation).  No atomics.
 #include "common.hpp"
 #include "pair_once.hpp"
+#include "wave_sum.hpp"
 
 #include <cstring>
 
@@ -208,6 +209,64 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BwdArgs P)
             P.gx[3 * i + 2] = gz;
             if (P.gm) P.gm[i] = c.G;
         }
+    }
+}
+
+// Row-per-wave adjoint for the smallest n, where launch latency and the
+// longest dependent chain set the time: wave w owns rows [K w, K w + K)
+// (the same for every lane), lane l gathers j = l, l + 64, ... into each
+// row's sums A, B, C, G, and a fixed butterfly adds the 64 lane sums
+// (bitwise reproducible).  One launch, no LDS, no partials.
+template <int K>
+__global__ __launch_bounds__(256) void backward_row_kernel(BwdArgs P)
+{
+    const int n = P.n;
+    const float eps2 = P.eps2;
+    const int lane = threadIdx.x & 63;
+    const int i0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6))) * K;
+    if (i0 >= n) return;  // the whole wave: no barrier follows
+    float4 xk[K], wk[K];
+    RowAcc acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int ic = min(i0 + k, n - 1);  // rows past n are computed, not stored
+        xk[k] = load_xm(P, ic);
+        wk[k] = load_wv(P, ic);
+        zero(acc[k]);
+    }
+#pragma unroll 2
+    for (int j = lane; j < n; j += 64) {
+        const float4 q = load_xm(P, j);
+        const float4 wq = load_wv(P, j);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            adj_term(xk[k].x, xk[k].y, xk[k].z, xk[k].w, wk[k].x, wk[k].y, wk[k].z, wk[k].w, q,
+                     wq, eps2, j == i0 + k, acc[k]);
+    }
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        RowAcc c = acc[k];
+        c.A = wave_sum(c.A);
+        c.Bx = wave_sum(c.Bx);
+        c.By = wave_sum(c.By);
+        c.Bz = wave_sum(c.Bz);
+        c.Cx = wave_sum(c.Cx);
+        c.Cy = wave_sum(c.Cy);
+        c.Cz = wave_sum(c.Cz);
+        c.G = wave_sum(c.G);
+        // dL/dx_k = w_k A - m_k B - C
+        const float4 g = make_float4(wk[k].x * c.A - xk[k].w * c.Bx - c.Cx,
+                                     wk[k].y * c.A - xk[k].w * c.By - c.Cy,
+                                     wk[k].z * c.A - xk[k].w * c.Bz - c.Cz, c.G);
+        if (lane == k) out = g;  // lane k stores row i0 + k
+    }
+    const int i = i0 + lane;
+    if (lane < K && i < n) {
+        P.gx[3 * i + 0] = out.x;
+        P.gx[3 * i + 1] = out.y;
+        P.gx[3 * i + 2] = out.z;
+        if (P.gm) P.gm[i] = out.w;
     }
 }
 
@@ -661,6 +720,8 @@ struct Variant {
     SymRunFn sym;
     SymKernelFn sym_kernel;
     int sym_w, sym_k, sym_occ, sym_rounds;
+    KernelFn row;  // row-per-wave kernel (K = row_k rows per wave)
+    int row_k;
 };
 
 #define BWD_VARIANT(B, K, U) \
@@ -672,6 +733,9 @@ struct Variant {
 #define BWD_SYM_R_VARIANT(W, K, R) \
     {"bwd_sym_w" #W "_k" #K "_r" #R, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, 1, R>, \
      backward_sym_kernel<W, K, true>, W, K, 1, R}
+
+#define BWD_ROW_VARIANT(K) \
+    {"bwd_row_k" #K, 64, K, 0, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 1, backward_row_kernel<K>, K}
 
 const Variant kVariants[] = {
     BWD_VARIANT(256, 2, 4),
@@ -695,6 +759,8 @@ const Variant kVariants[] = {
     BWD_SYM_R_VARIANT(1, 2, 8),
     BWD_SYM_R_VARIANT(2, 2, 8),
     BWD_SYM_R_VARIANT(2, 1, 8),
+    BWD_ROW_VARIANT(1),
+    BWD_ROW_VARIANT(2),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -714,7 +780,8 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once adjoint wins from 2^11 particles on; its
+// Measured on MI355X: the pair-once adjoint wins from about 4,800 particles
+// on, one wave per row below; its
 // workspace is bounded as the forward's (ring groups), and above 2^24
 // particles the gather kernel takes over.  Without potential weights
 // (grad_p NULL) each pair costs fewer registers and one-wave blocks of 128
@@ -729,7 +796,8 @@ int backward_default_variant(int64_t n, bool has_v)
     static const int pair_once_nov_small = variant_index("bwd_sym_w2_k1_r8");
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
-    static const int gather_small = variant_index("bwd_b128_k1_u8");
+    static const int row_1 = variant_index("bwd_row_k1");
+    static const int row_2 = variant_index("bwd_row_k2");
     if (n > (1 << 24)) return gather;
     // eight rounds of one-wave workgroups (down to one tile each, which the
     // dispatcher hands out as slots free up): 4-9% faster than one round
@@ -741,8 +809,12 @@ int backward_default_variant(int64_t n, bool has_v)
     if (n >= (1 << 16)) return pair_once;
     if (has_v && n >= 10000 && n < 24576) return pair_once_r8;
     if (has_v && n >= 14000) return pair_once_mid;
-    if (n >= (1 << 11)) return pair_once_small;
-    return gather_small;
+    // one wave per row below 4,800 bodies (two rows from 3,500): 4.7 against
+    // 16.1 us per call at 1,024 (split gather and its reduction), 18.3
+    // against 21.8 at 4,096 (pair-once and its fold), 34.5 against 29.3 at
+    // 6,000
+    if (n >= 4800) return pair_once_small;
+    return n >= 3500 ? row_2 : row_1;
 }
 
 // Geometry of the row gather: j-splits and j per split.
@@ -768,6 +840,7 @@ int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
         return -1;
     if (n == 0) return 0;
     const Variant &V = kVariants[variant];
+    if (V.row) return 0;
     if (V.sym) {
         SymPlan pl;
         if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu * V.sym_rounds, V.sym_occ,
@@ -782,15 +855,18 @@ int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
 
 int64_t backward_variant_max_n(int variant)
 {
-    return (variant < 0 || variant >= kNumVariants) ? -1 : NBODY_MAX_N;
+    if (variant < 0 || variant >= kNumVariants) return -1;
+    // the row-per-wave kernels are built for launch-latency-bound sizes
+    return kVariants[variant].row ? (1 << 16) : NBODY_MAX_N;
 }
 
 nbody_status backward_variant_occupancy(int variant, int *per_cu)
 {
     const Variant &V = kVariants[variant];
     const hipError_t e =
-        V.sym ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.sym_kernel, V.sym_w * 64, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.partial, V.block, 0);
+        V.sym   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.sym_kernel, V.sym_w * 64, 0)
+        : V.row ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.row, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.partial, V.block, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (*per_cu < 1) *per_cu = 1;
     return NBODY_OK;
@@ -803,6 +879,15 @@ nbody_status backward_run(int variant, const Device &dev, const float *x, const 
     const Variant &V = kVariants[variant];
     if (fused) *fused = false;
     if (V.sym) return V.sym(V.name, dev, x, m, n, eps2, ga, gp, gx, gm, stream, epi, fused, arena);
+    if (V.row) {
+        const int64_t waves = ((int64_t)n + V.row_k - 1) / V.row_k;
+        BwdArgs P{x, m, ga, gp, n, eps2, 0, nullptr, gx, gm};
+        if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
+        hipLaunchKernelGGL(V.row, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, P);
+        prof_mark(stream, 1);
+        return check_launch(V.name);
+    }
     const int iblk = V.block * V.k;
     const int iblocks = (n + iblk - 1) / iblk;
     int splits = 1, chunk = 0;

@@ -27,6 +27,7 @@
 // and split count.
 #include "common.hpp"
 #include "pair_once.hpp"
+#include "wave_sum.hpp"
 
 #include <algorithm>
 #include <cstdio>
@@ -326,6 +327,77 @@ __global__ __launch_bounds__(W * 64) void forward_la_kernel(LaArgs P)
     if (lane == 0) atomicExch(&P.ctr[blockIdx.x], 0);
 }
 
+// ---------------------------------------------------------------------------
+// Row-per-wave kernel for the smallest n (up to a few thousand bodies),
+// where one call costs launch latency plus its longest chain of dependent
+// steps rather than pairs.  Wave w owns rows [K w, K w + K): their
+// positions are the same for every lane (scalar registers) and lane l sums
+// j = l, l + 64, l + 128, ... for all K rows.  The 64 lane sums of a row
+// are then added by a fixed butterfly (DPP within rows of 16 lanes, then
+// two lane swaps), so every lane ends with the same, bitwise reproducible
+// total.  No LDS tile, no partials, no ticket and no second launch: at
+// n = 1,024 with K = 1 the 1,024 waves give every SIMD of the chip one.
+struct RowArgs {
+    const float *x;
+    const float *m;
+    int n;
+    float eps2;
+    float *a;
+    float *p;
+};
+
+template <int K>
+__global__ __launch_bounds__(256) void forward_row_kernel(RowArgs P)
+{
+    const int n = P.n;
+    const float eps2 = P.eps2;
+    const int lane = threadIdx.x & 63;
+    const int i0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6))) * K;
+    if (i0 >= n) return;  // the whole wave: no barrier follows
+    float xi[K], yi[K], zi[K], ax[K], ay[K], az[K], ap[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int ik = min(i0 + k, n - 1);  // rows past n are computed, not stored
+        xi[k] = P.x[3 * ik];
+        yi[k] = P.x[3 * ik + 1];
+        zi[k] = P.x[3 * ik + 2];
+        ax[k] = ay[k] = az[k] = ap[k] = 0.f;
+    }
+#pragma unroll 4
+    for (int j = lane; j < n; j += 64) {
+        const float4 q = make_float4(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.m[j]);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            pair_term_masked(xi[k], yi[k], zi[k], q, eps2, j == i0 + k, ax[k], ay[k], az[k], ap[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        ax[k] = wave_sum(ax[k]);
+        ay[k] = wave_sum(ay[k]);
+        az[k] = wave_sum(az[k]);
+        ap[k] = wave_sum(ap[k]);
+    }
+    // lane k stores row i0 + k
+    float sx = ax[0], sy = ay[0], sz = az[0], sp = ap[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k)
+        if (lane == k) {
+            sx = ax[k];
+            sy = ay[k];
+            sz = az[k];
+            sp = ap[k];
+        }
+    const int i = i0 + lane;
+    if (lane < K && i < n) {
+        P.a[3 * i + 0] = sx;
+        P.a[3 * i + 1] = sy;
+        P.a[3 * i + 2] = sz;
+        if (P.p) P.p[i] = sp;
+    }
+}
+
+using RowFn = void (*)(RowArgs);
+
 using LaFn = void (*)(LaArgs);
 
 using KernelFn = void (*)(FwdArgs);
@@ -342,6 +414,8 @@ struct Variant {
     int la_w;
     bool d64;     // float64 running sums (forward_kernel's D64)
     bool la_one;  // one-launch kernel with a single split: no partials, no ticket
+    RowFn row;    // row-per-wave kernel (K = row_k rows per wave)
+    int row_k;
 };
 
 #define FWD_VARIANT(B, K, U) \
@@ -356,6 +430,7 @@ struct Variant {
 // The same kernel with one split: the W waves of a row block's workgroup
 // share all of j, and their wave-ordered sum is the result.
 #define FWD_LA1_VARIANT(W) {"fwd_la1_w" #W, 64, 1, 0, nullptr, nullptr, 0, 0, 0, 1, forward_la_kernel<W>, W, false, true}
+#define FWD_ROW_VARIANT(K) {"fwd_row_k" #K, 64, K, 0, nullptr, nullptr, 0, 0, 0, 1, nullptr, 0, false, false, forward_row_kernel<K>, K}
 
 const Variant kVariants[] = {
     // The paper's three GPU programs as (rows per lane K, j-unroll U):
@@ -391,6 +466,9 @@ const Variant kVariants[] = {
     FWD_LA_VARIANT(16),
     FWD_LA1_VARIANT(8),
     FWD_LA1_VARIANT(16),
+    FWD_ROW_VARIANT(1),
+    FWD_ROW_VARIANT(2),
+    FWD_ROW_VARIANT(4),
     // float64 running sums, for accuracy at very large n
     FWD_D64_VARIANT(256, 1, 8),
     FWD_D64_VARIANT(64, 1, 8),
@@ -414,16 +492,18 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once kernel wins from about 3,000 particles
-// on.  Its workspace is bounded (ring groups, about 1 GiB up to 2^22
-// particles, 256 n bytes above); beyond 2^24 particles, where a group would
-// hold very few ring offsets, the float64-sum gather takes over.
+// Measured on MI355X: the pair-once kernel wins from about 5,500 particles
+// on, one wave per row below.  Its
+// workspace is bounded (ring groups, about 1 GiB up to 2^22 particles,
+// 256 n bytes above); beyond 2^24 particles, where a group would hold very
+// few ring offsets, the float64-sum gather takes over.
 int forward_default_variant(int64_t n)
 {
     // The gather keeps float64 row sums: as fast as float32 sums and
     // 10-100x more accurate above a million bodies.
     static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
-    static const int one_launch = variant_index("fwd_la_w16");
+    static const int row_1 = variant_index("fwd_row_k1");
+    static const int row_2 = variant_index("fwd_row_k2");
     static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_r8");
     static const int pair_once_1 = variant_index("fwd_sym_w1_k4_r8");
@@ -443,9 +523,17 @@ int forward_default_variant(int64_t n)
     // one-wave blocks of 128 particles: twice the workgroups of 256-particle
     // blocks, which evens out the one round of workgroups these sizes fill
     // (3-17% faster from 3,000 to 10,000 bodies, slower from about 12,000)
-    if (n >= 3000) return pair_once_small;
-    // Small n is set by launch latency: one launch, no reduction kernel.
-    return one_launch;
+    // Small n is set by launch latency and the longest dependent chain: one
+    // wave per row (two rows from 3,000 bodies), no LDS, no second launch.
+    // Kernel 3.4 us at 1,024 bodies against 7.1 us for the one-launch split
+    // gather.  Against the pair-once kernel and its fold the row kernel
+    // leads a plain call up to about 6,500 bodies (18.3 against 21.1 us at
+    // 6,000) but a leap-frog step, whose update the pair-once fold applies
+    // in place and the row kernel needs a launch for, only up to about
+    // 4,500 (19.7 against 17.3 us at 5,000); both use one choice, so that a
+    // leap-frog call stays bitwise the composed calls.
+    if (n >= 5500) return pair_once_small;
+    return n >= 3000 ? row_2 : row_1;
 }
 
 bool forward_variant_f64sum(int v) { return v >= 0 && v < kNumVariants && kVariants[v].d64; }
@@ -507,6 +595,7 @@ int64_t forward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
     if (n == 0) return 0;
     const Variant &V = kVariants[variant];
     int splits = 1, chunk = 0;
+    if (V.row) return 0;
     if (V.la_w) {
         la_geometry(V, (int)n, num_cu, &splits, &chunk);
         return splits > 1 ? (int64_t)sizeof(float4) * splits * n : 0;
@@ -527,7 +616,7 @@ int64_t forward_variant_max_n(int variant)
 {
     if (variant < 0 || variant >= kNumVariants) return -1;
     // the one-launch kernels are built for launch-latency-bound sizes
-    return kVariants[variant].la_w ? (1 << 16) : NBODY_MAX_N;
+    return (kVariants[variant].la_w || kVariants[variant].row) ? (1 << 16) : NBODY_MAX_N;
 }
 
 nbody_status forward_variant_occupancy(int variant, int *per_cu)
@@ -535,7 +624,9 @@ nbody_status forward_variant_occupancy(int variant, int *per_cu)
     const Variant &V = kVariants[variant];
     hipError_t e;
     if (V.sym_w) return forward_sym_occupancy(V.sym_w, V.sym_k, per_cu);
-    if (V.la_w)
+    if (V.row)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.row, 256, 0);
+    else if (V.la_w)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.la, V.la_w * 64, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, V.partial, V.block, 0);
@@ -550,6 +641,15 @@ nbody_status forward_run(int variant, const Device &dev, const float *x, const f
 {
     const Variant &V = kVariants[variant];
     if (fused) *fused = false;
+    if (V.row) {
+        const int64_t waves = ((int64_t)n + V.row_k - 1) / V.row_k;
+        RowArgs P{x, m, n, eps2, a, p};
+        if (fault_injected("launch")) return fail(NBODY_ERROR_LAUNCH_FAILED, "injected launch fault");
+        prof_mark(stream, 0);
+        hipLaunchKernelGGL(V.row, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, P);
+        prof_mark(stream, 1);
+        return check_launch(V.name);
+    }
     if (V.la_w) {
         const int rb = (n + 63) / 64;
         int splits = 1, chunk = 0;

@@ -108,11 +108,20 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else t.data_ptr()
 
 
+_ONE_DEVICE = None
+
+
 def _on(device: torch.device):
     """Make ``device`` current for the call (a no-op when it already is)."""
-    if device.index is None or device.index == torch.cuda.current_device():
-        return contextlib.nullcontext()
+    global _ONE_DEVICE
+    if _ONE_DEVICE is None:
+        _ONE_DEVICE = torch.cuda.device_count() == 1
+    if _ONE_DEVICE or device.index is None or device.index == torch.cuda.current_device():
+        return _NULL
     return torch.cuda.device(device)
+
+
+_NULL = contextlib.nullcontext()
 
 
 # torch's current-stream handle without building a Stream object (the
@@ -126,7 +135,16 @@ def _stream(device: torch.device):
     return torch.cuda.current_stream(device).cuda_stream
 
 
+_F32 = torch.float32
+
+
 def _want(t: torch.Tensor, name: str, shape, device=None) -> None:
+    # the common case in one expression (a small call spends more time here
+    # than in the library); anything else goes through the checks below,
+    # which name what is wrong
+    if (type(t) is torch.Tensor and t.is_cuda and t.dtype is _F32 and t.is_contiguous()
+            and t.shape == shape and (device is None or t.get_device() == device.index)):
+        return
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.device.type != "cuda":

@@ -149,6 +149,40 @@ def test_pair_once_block_rings(nb, n):
         nb.set_variant(nb.BACKWARD, -1)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1000, 3001, 6001])
+def test_row_per_wave_adjoint(nb, n):
+    # one wave per row (or per K rows), lanes splitting j: parity with and
+    # without each upstream, bitwise repeatability, absent weights equal to
+    # explicit zeros bitwise, and nothing stored past row n
+    dev = need_gpu()
+    x, m, w, v = _system(n, 70 + n)
+    xd, md, wd, vd = to_dev(x, dev), to_dev(m, dev), to_dev(w, dev), to_dev(v, dev)
+    names = nb.variant_names(nb.BACKWARD)
+    rows = [nm for nm in names if nm.startswith("bwd_row")]
+    assert rows
+    try:
+        for name in rows:
+            nb.set_variant(nb.BACKWARD, names.index(name))
+            for ww, vv, label in ((w, v, "w, v"), (w, None, "w"), (None, v, "v")):
+                gx, gm = _grad(nb, x, m, 1e-3, ww, vv, dev)
+                if n > 1:
+                    rx, rm = R.forces_vjp(x, m, 1e-3, ww, vv)
+                    _check(gx, gm, rx, rm, f"{name} n={n} {label}")
+                else:
+                    assert not gx.any() and not gm.any()
+            gx1 = torch.full((n + 4, 3), 5.0, device=dev)
+            gm1 = torch.full((n + 4,), 5.0, device=dev)
+            nb.forces_backward(xd, md, 1e-3, wd, vd, out=(gx1[:n], gm1[:n]))
+            gx2, gm2 = nb.forces_backward(xd, md, 1e-3, wd, vd)
+            assert torch.equal(gx1[:n], gx2) and torch.equal(gm1[:n], gm2), name
+            assert bool((gx1[n:] == 5.0).all()) and bool((gm1[n:] == 5.0).all()), name
+            gx3, gm3 = nb.forces_backward(xd, md, 1e-3, wd, None)
+            gx4, gm4 = nb.forces_backward(xd, md, 1e-3, wd, torch.zeros((n,), device=dev))
+            assert torch.equal(gx3, gx4) and torch.equal(gm3, gm4), name
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+
+
 @pytest.mark.parametrize("n", [16384, 70000])
 def test_no_potential_weights_kernel(nb, n):
     # grad_p None takes the pair-once kernel that does not form the

@@ -177,18 +177,21 @@ def test_invalid_arguments(nb):
     assert ei.value.status == 1
 
 
-@pytest.mark.parametrize("variant", [None, "fwd_b256_k1_u8", "fwd_la_w16"])
+@pytest.mark.parametrize("variant", [None, "fwd_b256_k1_u8", "fwd_la_w16", "fwd_row_k2"])
 def test_fault_injection_then_recovery(nb, variant):
-    # n = 5000 makes every split gather allocate its partial-sum workspace
+    # n = 5000 makes every split gather allocate its partial-sum workspace,
+    # and n = 7000 the default pair-once kernel; the row-per-wave kernels
+    # allocate nothing, so only their launch can fail
     dev = need_gpu()
-    n = 5000
+    n = 7000 if variant is None else 5000
     x = to_dev(inputs.plummer_positions(n, (62, n)), dev)
     m = to_dev(inputs.equal_masses(n), dev)
     names = nb.variant_names(nb.FORWARD)
     nb.set_variant(nb.FORWARD, -1 if variant is None else names.index(variant))
+    faults = (("launch", 4),) if variant and variant.startswith("fwd_row") else (("launch", 4), ("alloc", 3))
     try:
         good, _ = nb.forces(x, m, 1e-4)
-        for what, status in (("launch", 4), ("alloc", 3)):
+        for what, status in faults:
             os.environ["NBODY_FAULT"] = what
             try:
                 with pytest.raises(nb.NBodyError) as ei:
@@ -231,8 +234,14 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
     assert names[nb.selected_variant(nb.FORWARD, 1 << 24)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, (1 << 24) + 1)].startswith("fwd_sym")
-    # one-launch split gather: no reduction launch for small n
-    assert names[nb.selected_variant(nb.FORWARD, 1024)].startswith("fwd_la")
+    # one wave per row (two rows from 3,000 bodies) below 5,500 bodies
+    assert names[nb.selected_variant(nb.FORWARD, 1024)] == "fwd_row_k1"
+    assert names[nb.selected_variant(nb.FORWARD, 4096)] == "fwd_row_k2"
+    assert names[nb.selected_variant(nb.FORWARD, 5500)].startswith("fwd_sym")
+    b = nb.variant_names(nb.BACKWARD)
+    assert b[nb.selected_variant(nb.BACKWARD, 1024)] == "bwd_row_k1"
+    assert b[nb.selected_variant(nb.BACKWARD, 4096)] == "bwd_row_k2"
+    assert b[nb.selected_variant(nb.BACKWARD, 4800)].startswith("bwd_sym")
 
 
 def test_profile_hook(nb):
@@ -275,6 +284,36 @@ def test_one_launch_split_gather(nb, n):
             a3, p3 = nb.forces(xs, ms, 1e-4)
             ar3, pr3 = R.forces(host(xs), host(ms), 1e-4)
             assert_parity(host(a3), host(p3), ar3, pr3, label=f"{name} n=333 after n={n}")
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 127, 1000, 1024, 2049, 4097, 20000])
+def test_row_per_wave(nb, n):
+    # one wave per row (or per K rows), lanes splitting j, a fixed butterfly
+    # over the 64 lane sums: parity, bitwise repeatability, the same a with
+    # and without p, and rows past n (n not a multiple of K) never stored
+    dev = need_gpu()
+    x = inputs.plummer_positions(n, (66, n))
+    m = inputs.lognormal_masses(n, (66, n, 1))
+    ar, pr = R.forces(x, m, 1e-4)
+    names = nb.variant_names(nb.FORWARD)
+    xd, md = to_dev(x, dev), to_dev(m, dev)
+    rows = [nm for nm in names if nm.startswith("fwd_row")]
+    assert rows
+    try:
+        for name in rows:
+            nb.set_variant(nb.FORWARD, names.index(name))
+            a1 = torch.full((n + 8, 3), 7.0, device=dev)
+            p1 = torch.full((n + 8,), 7.0, device=dev)
+            nb.forces(xd, md, 1e-4, out=(a1[:n], p1[:n]))
+            a2, p2 = nb.forces(xd, md, 1e-4)
+            a3, p3 = nb.forces(xd, md, 1e-4, potential=False)
+            assert p3 is None
+            assert torch.equal(a1[:n], a2) and torch.equal(p1[:n], p2), name
+            assert torch.equal(a2, a3), name
+            assert bool((a1[n:] == 7.0).all()) and bool((p1[n:] == 7.0).all()), name
+            assert_parity(host(a2), host(p2), ar, pr, label=f"{name} n={n}")
     finally:
         nb.set_variant(nb.FORWARD, -1)
 

@@ -1,7 +1,7 @@
 """Library calls captured in a HIP graph (torch.cuda.CUDAGraph) and replayed:
 every replay must reproduce the eager result bitwise, with eager work between
-the replays, for each kernel family (one-launch, split-gather, pair-once
-forward; pair-once adjoint; persistent batched with its ticket counters; the
+the replays, for each kernel family (row-per-wave and pair-once forward;
+pair-once adjoint; persistent batched with its ticket counters; the
 device-resident leap-frog segments and their reverse sweep)."""
 
 import numpy as np
@@ -86,9 +86,9 @@ def test_batched_graph(nb):
 def test_leapfrog_graphs(nb, n):
     # whole leap-frog segments captured as one graph: the forward steps with
     # their position history, and the reverse sweep; n = 1500 runs the
-    # one-launch force and gather adjoint (element-wise update launches,
-    # the adjoint's auxiliary buffer), n = 20000 the pair-once kernels with
-    # the updates in their reduction epilogue
+    # row-per-wave force and adjoint (element-wise update launches, the
+    # adjoint's auxiliary buffer), n = 20000 the pair-once kernels with the
+    # updates in their reduction epilogue
     dev = need_gpu()
     x0 = to_dev(inputs.plummer_positions(n, (75, n)), dev)
     v0 = to_dev(inputs.plummer_velocities(inputs.plummer_positions(n, (75, n)), (75, n, 1)), dev)

@@ -139,8 +139,8 @@ def test_kick_drift_matches_two_axpys(nb):
 def test_graph_replay_equals_eager(nb, n, steps, k):
     # HIP-graph segments (forward k steps, position recomputation, interior
     # reverse sweep) against the eager launches: bitwise, for a loss on both
-    # x_T and v_T, a ragged last segment (20 = 2 x 8 + 4) and the one-launch,
-    # split-gather and pair-once force kernels
+    # x_T and v_T, a ragged last segment (20 = 2 x 8 + 4) and the
+    # row-per-wave and pair-once force and adjoint kernels
     dev = need_gpu()
     x, v, m, u = _case(n, 6)
     uv = inputs.normal(x.shape, (73, n))
@@ -198,7 +198,7 @@ def _forced(nb, kind, name):
 @pytest.mark.parametrize("n,variant,steps", [
     (1, None, 5), (2, None, 3), (700, None, 5), (4099, None, 5), (6001, None, 5),
     (20000, None, 5), (70001, None, 5), (3001, None, 1), (700, None, 1),
-    (6001, "fwd_la_w16", 5), (6001, "fwd_b256_k1_u8", 5), (9000, "fwd_b64_k1_u8_f64sum", 5),
+    (6001, "fwd_la_w16", 5), (6001, "fwd_row_k1", 5), (6001, "fwd_b256_k1_u8", 5), (9000, "fwd_b64_k1_u8_f64sum", 5),
     (9000, "fwd_sym_w8_k4_o1", 5), (3000, "fwd_sym_w4_k4_o1", 5)])
 def test_leapfrog_call_equals_composed_calls(nb, n, variant, steps):
     dev = need_gpu()

@@ -26,8 +26,8 @@ def _case(n, key, dev):
 
 
 def test_two_streams_overlap(nb):
-    # a pair-once, a one-launch and a split-gather evaluation in flight on
-    # two streams at once
+    # pair-once evaluations of three block shapes and a row-per-wave one in
+    # flight on two streams at once
     dev = need_gpu()
     cases = [_case(n, k, dev) for k, n in enumerate((40000, 3000, 9000, 20000))]
     ref = [nb.forces(x, m, 1e-4) for x, m in cases]

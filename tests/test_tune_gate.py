@@ -68,7 +68,7 @@ def test_gate_size_band_and_cap(L):
     fwd = names(L, 0)
     n = 1 << 20
     # the one-launch kernels are not timed beyond their size band
-    for name in [v for v in fwd if v.startswith("fwd_la")]:
+    for name in [v for v in fwd if v.startswith(("fwd_la", "fwd_row"))]:
         b, timed = plan(L, 0, name, n, 4)
         assert b >= 0 and timed == 0, name
         assert plan(L, 0, name, 1 << 14, 4)[1] == 1, name
