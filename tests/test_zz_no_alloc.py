@@ -1,5 +1,6 @@
 """nbody_forces_noalloc (the forward with its workspace in the library's
-fixed device region) against nbody_forces, through the C ABI."""
+fixed device region) against nbody_forces, through the C ABI, and captured
+in a HIP graph (torch.cuda.CUDAGraph) and replayed."""
 
 import numpy as np
 import pytest
@@ -79,6 +80,41 @@ def test_ring_split_to_fit_the_region(nb):
     # workspace fits the region at this size)
     x, m, a, p, a_ref, p_ref = _pair(nb, 3001, 10, dev)
     assert torch.equal(a, a_ref) and torch.equal(p, p_ref)
+
+
+@pytest.mark.parametrize("n", [1000, 9000, 20000, 150001])
+def test_captured_noalloc_replays(nb, n):
+    # 1,000: the row-per-wave kernel; 9,000: the pair-once kernel in one
+    # ring group; 20,000 and 150,001: the ring split into several groups to
+    # fit the region, with the float64 running sum between them
+    dev = need_gpu()
+    print(f"[noalloc capture] n={n}", flush=True)
+    x = to_dev(inputs.plummer_positions(n, (82, n)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (82, n, 1)), dev)
+    a_ref = torch.full((n, 3), float("nan"), device=dev)
+    p_ref = torch.full((n,), float("nan"), device=dev)
+    nb.forces_noalloc(x, m, 1e-4, a_ref, p_ref)
+    torch.cuda.synchronize()
+    a = torch.full((n, 3), float("nan"), device=dev)
+    p = torch.full((n,), float("nan"), device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        nb.forces_noalloc(x, m, 1e-4, a, p)
+    torch.cuda.synchronize()
+    xs = to_dev(inputs.plummer_positions(777, (82, 1)), dev)
+    ms = to_dev(inputs.equal_masses(777), dev)
+    for r in range(3):
+        a.fill_(float("nan"))
+        p.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a, a_ref) and torch.equal(p, p_ref), (n, r)
+        # eager work on the same region between the replays
+        a2 = torch.empty((777, 3), device=dev)
+        nb.forces_noalloc(xs, ms, 1e-4, a2)
+        torch.cuda.synchronize()
 
 
 def test_too_large_is_refused(nb):
