@@ -105,3 +105,16 @@ def test_bad_arguments(L):
     assert L.nbody_variant_plan(0, 0, 1000, 0, 2, GiB, None) == -1
     assert L.nbody_variant_plan(1, 0, 1000, 256, 0, GiB, None) == -1
     assert L.nbody_variant_plan(0, 0, 0, 256, 2, GiB, None) == 0
+
+
+@pytest.mark.parametrize("kind,prefix", [(0, "fwd_row"), (1, "bwd_row")])
+def test_row_per_wave_variants_need_no_workspace(L, kind, prefix):
+    # one wave per row: no partials, no counters at any size; timed only in
+    # the launch-latency band (up to 2^16 bodies)
+    rows = [v for v in names(L, kind) if v.startswith(prefix)]
+    assert rows
+    for name in rows:
+        for n in (1, 1000, 1 << 16):
+            assert plan(L, kind, name, n, 8) == (0, 1), (name, n)
+        assert plan(L, kind, name, (1 << 16) + 1, 8) == (0, 0), name
+        assert plan(L, kind, name, 1 << 20, 8) == (0, 0), name
