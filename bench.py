@@ -191,9 +191,10 @@ def timed_calls(fn, reps: int, torch, nb, events_in_timed_loop: bool = False):
     recorded on the stream it launches on (torch's current stream) around
     its pair kernel and after its last kernel.  With events_in_timed_loop
     they are recorded inside the timed loop itself (the 2^20 forward, where
-    they cost nothing measurable); otherwise a second loop of reps calls
-    records them, since at small n the records add several microseconds
-    per call to the loop they sit in."""
+    they cost nothing measurable); otherwise a second loop of min(reps, 256)
+    calls records them (the library keeps the last 256 calls' events),
+    since at small n the records add several microseconds per call to the
+    loop they sit in."""
     torch.cuda.synchronize()
     if events_in_timed_loop:
         nb.profile_enable(True)
@@ -202,14 +203,16 @@ def timed_calls(fn, reps: int, torch, nb, events_in_timed_loop: bool = False):
         fn()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    recorded = reps
     if not events_in_timed_loop:
+        recorded = min(reps, 256)
         nb.profile_enable(True)
-        for _ in range(reps):
+        for _ in range(recorded):
             fn()
         torch.cuda.synchronize()
     main_ms, total_ms, calls, launches = nb.profile_read(launches=True)
     nb.profile_enable(False)
-    assert calls == reps, (calls, reps)
+    assert calls == min(recorded, 256), (calls, recorded)
     timed_calls.launches = launches
     return wall, main_ms, total_ms
 

@@ -67,3 +67,36 @@ def test_cpu_baseline_keeps_its_oracle_rows():
 def test_hw_flop_is_keyed_like_traffic():
     for kind in ("forward", "adjoint", "batched"):
         assert bench.hw_flop(kind, "no_such_variant") is None
+
+
+def test_timed_calls_within_the_profiler_record():
+    # the library keeps the last 256 calls' events: a long timed loop is
+    # profiled on at most 256 calls, and a loop that records its own events
+    # reads back the last 256
+    class Torch:
+        class cuda:
+            @staticmethod
+            def synchronize():
+                pass
+
+    class NB:
+        def __init__(self):
+            self.on, self.calls = False, 0
+
+        def profile_enable(self, on):
+            self.on, self.calls = on, 0
+
+        def profile_read(self, launches=False):
+            c = min(self.calls, 256)
+            self.calls = 0
+            return (0.5, 0.6, c, 1.0)
+
+    nb = NB()
+
+    def fn():
+        if nb.on:
+            nb.calls += 1
+
+    for reps, inside in ((2000, False), (50, False), (300, True)):
+        wall, main_ms, total_ms = bench.timed_calls(fn, reps, Torch, nb, events_in_timed_loop=inside)
+        assert wall >= 0 and main_ms == 0.5 and total_ms == 0.6
