@@ -94,19 +94,20 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 3,000 <= n <= 2^24 the default variant evaluates each
+ * Kernels: for 5,500 <= n <= 2^24 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair), in blocks of P = 2048 particles from
- * 2^17 up, 1024 from 2^16, 256 from 12,000 and 128 below.  Each block meets
+ * 2^17 up, 1024 from 2^16, 256 from 24,576 and 128 below.  Each block meets
  * the blocks after it on a ring; the ring offsets run in groups, one launch
  * per group, each followed by a launch that adds the group's partial sums
  * to a float64 running sum per particle, so the library workspace stays at
  * most 1 GiB up to n = 2^22 (256 n bytes above; 0.86 GiB at n = 2^20).
- * Outside that range the default gathers every ordered pair per row with
- * j-splits: below 3,000 in one launch whose last workgroup per 64 rows adds
- * the splits (16 n * splits bytes of workspace and one int counter per 64
- * rows), above 2^24 with float64 row sums (as NBODY_FORCES_F64_SUM below)
- * and a reduction launch (at most 32 n * splits bytes).
+ * Outside that range the default evaluates every ordered pair: below 5,500
+ * in one launch with one wave per row (two rows from 3,000), its lanes
+ * splitting j and their sums added by a fixed in-register butterfly (no
+ * workspace); above 2^24 gathered per row with j-splits, float64 row sums
+ * (as NBODY_FORCES_F64_SUM below) and a reduction launch (at most
+ * 32 n * splits bytes).
  * Positions must be finite with magnitude below 1e17 (padding slots sit
  * at +-1e18 with zero mass).
  *
@@ -184,14 +185,16 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
  * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
- * Kernels: for 2^11 <= n <= 2^24 the default variant evaluates each
+ * Kernels: for 4,800 <= n <= 2^24 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair),
  * for blocks of P = 1024 particles from 2^16 (from 2^17 without grad_p)
  * and of 128 or 256 below, with the ring groups and bounded workspace of
  * the pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it does not form the
  * potential-weight terms (with the same variant, bitwise the result of zero
- * weights) and the default may take other block shapes.  Otherwise every
- * ordered pair is gathered per row.
+ * weights) and the default may take other block shapes.  Below 4,800 one
+ * launch with one wave per row (two rows from 3,500) evaluates every
+ * ordered pair (no workspace); above 2^24 every ordered pair is gathered
+ * per row.
  */
 nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, float eps2,
                                    const float *grad_a, const float *grad_p,
