@@ -30,7 +30,10 @@ segment's positions and the reverse sweep over an interior segment are each
 captured once as a HIP graph on fixed device buffers and replayed once per
 segment, instead of issuing every launch from the host.  The graphs run the
 same kernels on the same data, so results are bitwise equal to the eager
-path (``graphs=False``).
+path (``graphs=False``).  In the reverse pass the recomputation of the
+next segment's positions (into the other of two position buffers) runs on
+a second stream while the current segment is swept, so each fills the
+other's partial-sum folds and the drain at the end of each pair kernel.
 """
 
 from __future__ import annotations
@@ -118,17 +121,19 @@ def reverse_sweep(saved, m, eps2, dt, steps, gx_T, gv_T, checkpoint_every):
 
 
 class SegmentGraphs:
-    """Three HIP graphs over fixed buffers for one (m, eps2, dt, k):
+    """HIP graphs over fixed buffers for one (m, eps2, dt, k):
 
-    ``fwd``  k steps on (x, v, a), with a = a(x) on entry and exit;
-    ``pos``  k steps from (pos[0], pv, pa), keeping pos[1..k];
-    ``rev``  the reverse sweep over an interior segment (global step > 0)
-             with positions pos[0..k].
+    ``fwd``     k steps on (x, v, a), with a = a(x) on entry and exit;
+    ``pos<b>``  k steps from (pos[b][0], pv[b], pa[b]), keeping
+                pos[b][1..k], for position buffers b = 0, 1;
+    ``rev<b>``  the reverse sweep over an interior segment (global step > 0)
+                with positions pos[b][0..k].
 
     Each graph is captured on a stream of its own after one eager run there,
     so the library workspace its kernels point at belongs to that stream and
-    is never regrown while the graph lives.  The buffers are scratch for one
-    call at a time (no concurrent use from several host threads).
+    is never regrown while the graph lives (graphs that run at the same time
+    never share workspace).  The buffers are scratch for one call at a time
+    (no concurrent use from several host threads).
     """
 
     def __init__(self, m, eps2: float, dt: float, k: int):
@@ -137,22 +142,30 @@ class SegmentGraphs:
         z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=dev)
         self.m, self.eps2, self.dt, self.k = m, eps2, dt, k
         self.x, self.v, self.a = z(n, 3), z(n, 3), z(n, 3)
-        self.pos = z(k + 1, n, 3)
-        self.px, self.pv, self.pa = z(n, 3), z(n, 3), z(n, 3)
+        self.pos = [z(k + 1, n, 3), z(k + 1, n, 3)]
+        self.px = [z(n, 3), z(n, 3)]
+        self.pv = [z(n, 3), z(n, 3)]
+        self.pa = [z(n, 3), z(n, 3)]
         self.lx, self.lv, self.lm = z(n, 3), z(n, 3), z(n)
-        self._graphs = {name: self._capture(fn, dev)
-                        for name, fn in (("fwd", self._fwd), ("pos", self._pos), ("rev", self._rev))}
+        # the stream the reverse pass recomputes positions on (default
+        # priority, as every stream here)
+        self.side = torch.cuda.Stream(device=dev)
+        fns = {"fwd": self._fwd}
+        for b in (0, 1):
+            fns[f"pos{b}"] = lambda b=b: self._pos(b)
+            fns[f"rev{b}"] = lambda b=b: self._rev(b)
+        self._graphs = {name: self._capture(fn, dev) for name, fn in fns.items()}
 
     def _fwd(self):
         _nb.leapfrog_(self.x, self.v, self.a, self.m, self.eps2, self.dt, self.k)
 
-    def _pos(self):
-        self.px.copy_(self.pos[0])
-        _nb.leapfrog_(self.px, self.pv, self.pa, self.m, self.eps2, self.dt, self.k,
-                      x_hist=self.pos[1:])
+    def _pos(self, b: int):
+        self.px[b].copy_(self.pos[b][0])
+        _nb.leapfrog_(self.px[b], self.pv[b], self.pa[b], self.m, self.eps2, self.dt, self.k,
+                      x_hist=self.pos[b][1:])
 
-    def _rev(self):
-        _nb.leapfrog_adjoint_(self.pos, self.m, self.eps2, self.dt, self.lx, self.lv, self.lm)
+    def _rev(self, b: int):
+        _nb.leapfrog_adjoint_(self.pos[b], self.m, self.eps2, self.dt, self.lx, self.lv, self.lm)
 
     @staticmethod
     def _capture(fn, dev):
@@ -169,14 +182,14 @@ class SegmentGraphs:
     def replay(self, name: str):
         self._graphs[name][0].replay()
 
-    def segment_positions(self, xs, vs, a0):
-        """pos[0..k] from (xs, vs, a0 = a(xs)) by one replay; (pv, pa) then
-        hold (v, a) after the k steps."""
-        self.pos[0].copy_(xs)
-        self.pv.copy_(vs)
-        self.pa.copy_(a0)
-        self.replay("pos")
-        return self.pos
+    def segment_positions(self, b: int, xs, vs, a0):
+        """pos[b][0..k] from (xs, vs, a0 = a(xs)) by one replay on the
+        current stream; (pv[b], pa[b]) then hold (v, a) after the k steps."""
+        self.pos[b][0].copy_(xs)
+        self.pv[b].copy_(vs)
+        self.pa[b].copy_(a0)
+        self.replay(f"pos{b}")
+        return self.pos[b]
 
 
 _GRAPH_CACHE: dict = {}
@@ -209,11 +222,11 @@ def integrate_graphs(G: SegmentGraphs, x0, v0, steps: int):
         if t < last:
             G.replay("fwd")
         elif steps - t == k:                 # a full last segment: keep its positions
-            pos = G.segment_positions(G.x, G.v, G.a)
+            pos = G.segment_positions(0, G.x, G.v, G.a)
             saved["tail"] = pos.clone()
             G.x.copy_(pos[k])
-            G.v.copy_(G.pv)
-            G.a.copy_(G.pa)
+            G.v.copy_(G.pv[0])
+            G.a.copy_(G.pa[0])
         else:
             count = steps - t
             tail = torch.empty((count + 1,) + tuple(G.x.shape), dtype=G.x.dtype, device=G.x.device)
@@ -226,7 +239,15 @@ def integrate_graphs(G: SegmentGraphs, x0, v0, steps: int):
 
 def reverse_sweep_graphs(G: SegmentGraphs, saved, steps, gx_T, gv_T):
     """``reverse_sweep`` with segments recomputed and interior segments swept
-    by G's graphs; bitwise equal to the eager sweep."""
+    by G's graphs; bitwise equal to the eager sweep.
+
+    The segments that need their positions recomputed take the two position
+    buffers in turn.  Each recomputation is replayed on G's side stream,
+    after the sweep that last read its buffer (an event on the sweep
+    stream), and is launched one segment ahead, so it runs while the
+    previous segment is swept; each sweep waits for its positions (an event
+    on the side stream).  Every kernel reads what it would read in the
+    serial order, so the result is bitwise the same."""
     k, m, eps2, dt = G.k, G.m, G.eps2, G.dt
     lx, lv, lm = G.lx, G.lv, G.lm
     if gx_T is not None:
@@ -239,16 +260,45 @@ def reverse_sweep_graphs(G: SegmentGraphs, saved, steps, gx_T, gv_T):
         lv.zero_()
     lm.zero_()
     last = _last_start(steps, k)
-    for s0 in reversed(range(0, steps, k)):
+    order = list(reversed(range(0, steps, k)))
+    rec = [s0 for s0 in order if s0 != last]      # interior segments are full
+    buf = {s0: i % 2 for i, s0 in enumerate(rec)}
+    main, side = torch.cuda.current_stream(m.device), G.side
+    side.wait_stream(main)                        # checkpoints and G's buffers are ready
+    ready, freed = {}, [None, None]
+
+    def launch(i):
+        if i >= len(rec):
+            return
+        s0, b = rec[i], buf[rec[i]]
+        with torch.cuda.stream(side):
+            if freed[b] is not None:
+                side.wait_event(freed[b])         # the sweep that last read buffer b
+            G.segment_positions(b, *saved[s0])
+            ready[s0] = torch.cuda.Event()
+            ready[s0].record(side)
+
+    launch(0)                                     # runs while the last segment is swept
+    for s0 in order:
         if s0 == last:
-            pos = saved["tail"]
+            pos, b = saved["tail"], None
         else:
-            pos = G.segment_positions(*saved[s0])    # interior segments are full
-            if s0 > 0:
-                G.replay("rev")
-                continue
-        _nb.leapfrog_adjoint_(pos, m, eps2, dt, lx, lv, lm,
-                              flags=_flags(s0, last, gv_T is not None))
+            i = rec.index(s0)
+            b = buf[s0]
+            main.wait_event(ready[s0])
+            pos = G.pos[b]
+            # the next recomputation takes the other buffer, whose last
+            # reader (the previous segment's sweep) has recorded freed[]
+            launch(i + 1)
+        if b is not None and s0 > 0:
+            G.replay(f"rev{b}")
+        else:
+            _nb.leapfrog_adjoint_(pos, m, eps2, dt, lx, lv, lm,
+                                  flags=_flags(s0, last, gv_T is not None))
+        if b is not None:
+            freed[b] = torch.cuda.Event()
+            freed[b].record(main)
+    main.wait_stream(side)
     return lx.clone(), lv.clone(), lm.clone()
 
 
