@@ -118,3 +118,14 @@ def test_row_per_wave_variants_need_no_workspace(L, kind, prefix):
             assert plan(L, kind, name, n, 8) == (0, 1), (name, n)
         assert plan(L, kind, name, (1 << 16) + 1, 8) == (0, 0), name
         assert plan(L, kind, name, 1 << 20, 8) == (0, 0), name
+
+
+@pytest.mark.parametrize("n", [20001, 70003, (1 << 20) + 7])
+def test_running_sum_is_aligned(L, n, monkeypatch):
+    # with the ring in several groups the float64 running sum (32 bytes per
+    # particle, read as double4) follows the partials, whose area is rounded
+    # up to 256 bytes so that it starts aligned also for odd n
+    monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * 7))
+    for name in ("fwd_sym_w8_k4_o1", "fwd_sym_w1_k2_r8"):
+        b, _ = plan(L, 0, name, n, 2)
+        assert b > 0 and (b - 32 * n) % 256 == 0 and b % 256 != 0, (name, n, b)
