@@ -793,7 +793,7 @@ int backward_default_variant(int64_t n, bool has_v)
     static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
     static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
     static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
-    static const int pair_once_nov_small = variant_index("bwd_sym_w2_k1_r8");
+    static const int pair_once_r8_small = variant_index("bwd_sym_w2_k1_r8");
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int row_1 = variant_index("bwd_row_k1");
@@ -803,9 +803,12 @@ int backward_default_variant(int64_t n, bool has_v)
     // dispatcher hands out as slots free up): 4-9% faster than one round
     // without potential weights from 9,000 to 2^17 bodies and 3-5% with them
     // from 10,000 to 24,575 (interleaved A/B); 16% for two-wave one-row
-    // blocks at 6,000 without them
-    if (!has_v && n >= 9000 && n < (1 << 17)) return pair_once_r8;
-    if (!has_v && n >= 6000 && n < 9000) return pair_once_nov_small;
+    // blocks at 6,000 without them.  A forced-variant sweep at 8,192 bodies
+    // put the one-wave two-row blocks 4% ahead of those without potential
+    // weights, and the two-wave one-row blocks in eight rounds 6% ahead of
+    // one round with them.
+    if (!has_v && n >= 8000 && n < (1 << 17)) return pair_once_r8;
+    if (n >= 6000 && n < (has_v ? 10000 : 8000)) return pair_once_r8_small;
     if (n >= (1 << 16)) return pair_once;
     if (has_v && n >= 10000 && n < 24576) return pair_once_r8;
     if (has_v && n >= 14000) return pair_once_mid;

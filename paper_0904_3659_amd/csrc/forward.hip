@@ -518,7 +518,8 @@ int forward_default_variant(int64_t n)
     // even out the tail: 2-8% faster from 16,384 to 65,536 bodies
     // (interleaved A/B in one process)
     if (n >= (1 << 16)) return pair_once_4;
-    if (n >= 24576) return pair_once_1;
+    // four-row one-wave blocks lead from about 20,000 (3% at 24,000)
+    if (n >= 20000) return pair_once_1;
     if (n >= 12000) return pair_once_1s;
     // one-wave blocks of 128 particles: twice the workgroups of 256-particle
     // blocks, which evens out the one round of workgroups these sizes fill
