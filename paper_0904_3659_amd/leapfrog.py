@@ -95,10 +95,26 @@ def _flags(s0: int, last: int, final_kick: bool) -> int:
     return f
 
 
+_SIDE_STREAMS: dict = {}
+
+
+def _side_stream(dev: torch.device) -> torch.cuda.Stream:
+    """One recomputation stream per device (default priority), so that the
+    library keeps one workspace for it."""
+    s = _SIDE_STREAMS.get(dev.index)
+    if s is None:
+        s = _SIDE_STREAMS[dev.index] = torch.cuda.Stream(device=dev)
+    return s
+
+
 def reverse_sweep(saved, m, eps2, dt, steps, gx_T, gv_T, checkpoint_every):
     """Adjoints (dL/dx0, dL/dv0, dL/dm) from the output adjoints (gx_T, gv_T).
 
-    Without gv_T the final end kick carries zero weight and is skipped."""
+    Without gv_T the final end kick carries zero weight and is skipped.  As
+    in ``reverse_sweep_graphs``, each segment's positions are recomputed on
+    a second stream one segment ahead of the sweep (each into a tensor of
+    its own, allocated there and recorded for the sweep stream); the result
+    is bitwise that of the serial order."""
     dev = m.device
     n = m.shape[0]
     lx = gx_T.detach().clone().contiguous() if gx_T is not None else torch.zeros((n, 3), device=dev)
@@ -108,15 +124,36 @@ def reverse_sweep(saved, m, eps2, dt, steps, gx_T, gv_T, checkpoint_every):
         return lx, lv, lm
     k = checkpoint_every
     last = _last_start(steps, k)
-    for s0 in reversed(range(0, steps, k)):
-        count = min(k, steps - s0)
+    order = list(reversed(range(0, steps, k)))
+    rec = [s0 for s0 in order if s0 != last]
+    main, side = torch.cuda.current_stream(dev), _side_stream(dev)
+    side.wait_stream(main)                        # checkpoints are ready
+    pending = {}
+
+    def launch(i):
+        if i >= len(rec):
+            return
+        s0 = rec[i]
+        xs, vs, a0 = saved[s0]
+        with torch.cuda.stream(side):
+            pos = _positions(xs, vs, a0, m, eps2, dt, min(k, steps - s0))
+            ev = torch.cuda.Event()
+            ev.record(side)
+        pos.record_stream(main)
+        pending[s0] = (pos, ev)
+
+    launch(0)                                     # runs while the last segment is swept
+    for s0 in order:
         if s0 == last:
-            pos = saved["tail"]                          # kept by the forward pass
+            pos = saved["tail"]                   # kept by the forward pass
         else:
-            xs, vs, a0 = saved[s0]
-            pos = _positions(xs, vs, a0, m, eps2, dt, count)  # x_{s0} .. x_{s0+count}
+            i = rec.index(s0)
+            pos, ev = pending.pop(s0)
+            main.wait_event(ev)
+            launch(i + 1)
         _nb.leapfrog_adjoint_(pos, m, eps2, dt, lx, lv, lm,
                               flags=_flags(s0, last, gv_T is not None))
+    main.wait_stream(side)
     return lx, lv, lm
 
 
