@@ -97,11 +97,11 @@ const char *nbody_last_error(void);
  * Kernels: for 5,500 <= n <= 2^24 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair), in blocks of P = 2048 particles from
- * 2^17 up, 1024 from 2^16, 256 from 20,000 and 128 below.  Each block meets
+ * 2^20 up, 1024 from 2^16, 256 from 20,000 and 128 below.  Each block meets
  * the blocks after it on a ring; the ring offsets run in groups, one launch
  * per group, each followed by a launch that adds the group's partial sums
  * to a float64 running sum per particle, so the library workspace stays at
- * most 1 GiB up to n = 2^22 (256 n bytes above; 0.86 GiB at n = 2^20).
+ * most 1 GiB up to n = 2^22 (256 n bytes above; 0.97 GiB at n = 2^20).
  * Outside that range the default evaluates every ordered pair: below 5,500
  * in one launch with one wave per row (two rows from 3,000), its lanes
  * splitting j and their sums added by a fixed in-register butterfly (no
@@ -187,8 +187,8 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
  * Kernels: for 4,800 <= n <= 2^24 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair),
- * for blocks of P = 1024 particles from 2^16 (from 2^17 without grad_p)
- * and of 128 or 256 below, with the ring groups and bounded workspace of
+ * for blocks of P = 1024 particles from 2^18, 512 from 2^16 and 128 or 256
+ * below, with the ring groups and bounded workspace of
  * the pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it does not form the
  * potential-weight terms (with the same variant, bitwise the result of zero
  * weights) and the default may take other block shapes.  Below 4,800 one

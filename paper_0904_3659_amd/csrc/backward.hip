@@ -759,6 +759,8 @@ const Variant kVariants[] = {
     BWD_SYM_R_VARIANT(1, 2, 8),
     BWD_SYM_R_VARIANT(2, 2, 8),
     BWD_SYM_R_VARIANT(2, 1, 8),
+    BWD_SYM_R_VARIANT(8, 2, 8),
+    BWD_SYM_R_VARIANT(4, 2, 8),
     BWD_ROW_VARIANT(1),
     BWD_ROW_VARIANT(2),
 };
@@ -790,7 +792,8 @@ static int variant_index(const char *name)
 // blocks lead.
 int backward_default_variant(int64_t n, bool has_v)
 {
-    static const int pair_once = variant_index("bwd_sym_w8_k2_o1");
+    static const int pair_once_big = variant_index("bwd_sym_w8_k2_r8");
+    static const int pair_once_large = variant_index("bwd_sym_w4_k2_r8");
     static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
     static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
     static const int pair_once_r8_small = variant_index("bwd_sym_w2_k1_r8");
@@ -807,11 +810,15 @@ int backward_default_variant(int64_t n, bool has_v)
     // put the one-wave two-row blocks 4% ahead of those without potential
     // weights, and the two-wave one-row blocks in eight rounds 6% ahead of
     // one round with them.
-    if (!has_v && n >= 8000 && n < (1 << 17)) return pair_once_r8;
+    // From 2^16 eight rounds of 4- and 8-wave blocks (forced-variant sweep,
+    // same box): 9-11% ahead of one round of 8-wave blocks at 2^17, 4-6% at
+    // 2^18, 3-7% at 2^19, with and without potential weights.
+    if (n >= (1 << 18)) return pair_once_big;
+    if (n >= (1 << 16)) return pair_once_large;
+    if (!has_v && n >= 8000) return pair_once_r8;
     if (n >= 6000 && n < (has_v ? 10000 : 8000)) return pair_once_r8_small;
-    if (n >= (1 << 16)) return pair_once;
     if (has_v && n >= 10000 && n < 24576) return pair_once_r8;
-    if (has_v && n >= 14000) return pair_once_mid;
+    if (has_v && n >= 24576) return pair_once_mid;
     // one wave per row below 4,800 bodies (two rows from 3,500): 4.7 against
     // 16.1 us per call at 1,024 (split gather and its reduction), 18.3
     // against 21.8 at 4,096 (pair-once and its fold), 34.5 against 29.3 at

@@ -461,6 +461,7 @@ const Variant kVariants[] = {
     FWD_SYM_R_VARIANT(1, 4, 8),
     FWD_SYM_R_VARIANT(1, 2, 8),
     FWD_SYM_R_VARIANT(4, 4, 8),
+    FWD_SYM_R_VARIANT(8, 4, 8),
     FWD_LA_VARIANT(4),
     FWD_LA_VARIANT(8),
     FWD_LA_VARIANT(16),
@@ -504,19 +505,23 @@ int forward_default_variant(int64_t n)
     static const int gather_big = variant_index("fwd_b64_k1_u8_f64sum");
     static const int row_1 = variant_index("fwd_row_k1");
     static const int row_2 = variant_index("fwd_row_k2");
-    static const int pair_once_8 = variant_index("fwd_sym_w8_k4_o1");
+    static const int pair_once_8 = variant_index("fwd_sym_w8_k4_r8");
     static const int pair_once_4 = variant_index("fwd_sym_w4_k4_r8");
     static const int pair_once_1 = variant_index("fwd_sym_w1_k4_r8");
     static const int pair_once_1s = variant_index("fwd_sym_w1_k2_r8");
     static const int pair_once_small = variant_index("fwd_sym_w1_k2_o1");
     if (n > (1 << 24)) return gather_big;
-    // 8-wave blocks of 2,048 particles, two workgroups per CU: 1% ahead of
-    // 16-wave blocks at 2^20 (same-box A/B, repeated)
-    if (n >= (1 << 17)) return pair_once_8;
-    // Below 2^17 a single round of workgroups holds only a few tiles each;
-    // eight rounds of shorter ones (down to one tile) let the dispatcher
-    // even out the tail: 2-8% faster from 16,384 to 65,536 bodies
-    // (interleaved A/B in one process)
+    // Eight rounds of workgroups (each block's tiles cut into eight times as
+    // many chunks as the device holds workgroups), which the dispatcher
+    // hands out as slots free up, also pay at large n, where one round
+    // leaves every workgroup a whole ring group of tiles and each launch
+    // ends on its slowest: forced-variant sweep, same box, 6.7% less time
+    // than one round at 2^20 for 8-wave blocks of 2,048 particles (the
+    // same five ring-group launches), and 4-wave blocks of 1,024 in eight
+    // rounds 1-7% ahead from 2^17 to 2^19 (up to 15% ahead of the 8-wave
+    // ones there).  Below 2^16 likewise 2-8% from 16,384 to 65,536
+    // (interleaved A/B in one process).
+    if (n >= (1 << 20)) return pair_once_8;
     if (n >= (1 << 16)) return pair_once_4;
     // four-row one-wave blocks lead from about 20,000 (3% at 24,000)
     if (n >= 20000) return pair_once_1;

@@ -127,6 +127,7 @@ nbody_status forward_sym_run(int W, int K, int occ, int rounds, const char *name
         if (W == 1 && K == 4 && occ == 1) return run_sym<1, 4, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
         if (W == 1 && K == 2 && occ == 1) return run_sym<1, 2, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
         if (W == 4 && K == 4 && occ == 1) return run_sym<4, 4, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
+        if (W == 8 && K == 4 && occ == 1) return run_sym<8, 4, 1, 8>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);
         return fail(NBODY_ERROR_INTERNAL, "no pair-once forward kernel for W=%d K=%d occ=%d rounds=%d", W, K, occ, rounds);
     }
     if (W == 8 && K == 4 && occ == 1) return run_sym<8, 4, 1>(name, dev, x, m, n, eps2, a, p, stream, epi, fused, arena);

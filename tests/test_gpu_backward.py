@@ -236,6 +236,36 @@ def test_every_pair_once_variant_without_potential_weights(nb, n):
         nb.set_variant(nb.BACKWARD, -1)
 
 
+def test_large_n_defaults(nb):
+    # the eight-round defaults from 2^16: at 70,000 bodies (4-wave blocks)
+    # against the oracle; at 2^18 + 5 (8-wave blocks, ring groups) against
+    # the one-round kernel of the same blocks, which differs only in the
+    # order of its float32 partial sums
+    dev = need_gpu()
+    names = nb.variant_names(nb.BACKWARD)
+    n = 70000
+    x, m, w, v = _system(n, 71)
+    assert names[nb.selected_variant(nb.BACKWARD, n)] == "bwd_sym_w4_k2_r8"
+    gx, gm = _grad(nb, x, m, 1e-3, w, v, dev)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    _check(gx, gm, rx, rm, f"default n={n}")
+    n = (1 << 18) + 5
+    assert names[nb.selected_variant(nb.BACKWARD, n)] == "bwd_sym_w8_k2_r8"
+    x, m, w, v = (to_dev(t, dev) for t in _system(n, 72))
+    g_def = nb.forces_backward(x, m, 1e-4, w, v)
+    g_nov = nb.forces_backward(x, m, 1e-4, w, None)
+    nb.set_variant(nb.BACKWARD, names.index("bwd_sym_w8_k2_o1"))
+    try:
+        g_one = nb.forces_backward(x, m, 1e-4, w, v)
+        g_one_nov = nb.forces_backward(x, m, 1e-4, w, None)
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+    for a, b in zip(g_def + g_nov, g_one + g_one_nov):
+        e = ((a - b).abs().max() / b.abs().max()).item()
+        print(f"[large adjoint] n={n} eight rounds vs one: {e:.2e}", flush=True)
+        assert e <= 1e-5, e
+
+
 @pytest.mark.parametrize("n", [4097, 20000])
 def test_adjoint_ring_groups(nb, n, monkeypatch):
     # the adjoint's ring split into many launches by a small workspace
@@ -245,7 +275,8 @@ def test_adjoint_ring_groups(nb, n, monkeypatch):
     rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
     names = nb.variant_names(nb.BACKWARD)
     try:
-        for name in ("bwd_sym_w1_k2_o1", "bwd_sym_w2_k2_o1", "bwd_sym_w8_k2_o1"):
+        for name in ("bwd_sym_w1_k2_o1", "bwd_sym_w2_k2_o1", "bwd_sym_w8_k2_o1", "bwd_sym_w4_k2_r8",
+                     "bwd_sym_w8_k2_r8"):
             nb.set_variant(nb.BACKWARD, names.index(name))
             for slots in (5, 9):
                 monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * slots))

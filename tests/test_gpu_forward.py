@@ -375,7 +375,8 @@ def test_ring_groups(nb, n, monkeypatch):
     xd, md = to_dev(x, dev), to_dev(m, dev)
     names = nb.variant_names(nb.FORWARD)
     try:
-        for name in ("fwd_sym_w1_k2_o1", "fwd_sym_w4_k4_o1", "fwd_sym_w8_k4_o1"):
+        for name in ("fwd_sym_w1_k2_o1", "fwd_sym_w4_k4_o1", "fwd_sym_w8_k4_o1", "fwd_sym_w4_k4_r8",
+                     "fwd_sym_w8_k4_r8"):
             nb.set_variant(nb.FORWARD, names.index(name))
             for slots in (5, 7, 12):
                 monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * slots))

@@ -43,6 +43,10 @@ def test_pair_once_workspace_closed_form(L):
     n = 1 << 20
     b, _ = plan(L, 0, "fwd_sym_w8_k4_o1", n, 2)
     assert b == 53 * 16 * n + 32 * n
+    # eight rounds (the default here): 8 chunks per block, the same 5
+    # groups of 52 offsets, (8 + 52) slots plus the running sum
+    b, _ = plan(L, 0, "fwd_sym_w8_k4_r8", n, 2)
+    assert b == 60 * 16 * n + 32 * n
     # small n: the whole ring in one launch, no running sum: chunks fill the
     # 2 x 256 resident workgroups (M = 8 blocks -> 64 chunks, capped at the
     # 5 x 32 tiles of a block's sequence), plus 4 ring slots
