@@ -38,6 +38,8 @@ other's partial-sum folds and the drain at the end of each pair kernel.
 
 from __future__ import annotations
 
+import threading
+
 import torch
 
 from . import nbody as _nb
@@ -95,15 +97,20 @@ def _flags(s0: int, last: int, final_kick: bool) -> int:
     return f
 
 
-_SIDE_STREAMS: dict = {}
+_SIDE = threading.local()
 
 
 def _side_stream(dev: torch.device) -> torch.cuda.Stream:
-    """One recomputation stream per device (default priority), so that the
-    library keeps one workspace for it."""
-    s = _SIDE_STREAMS.get(dev.index)
+    """The recomputation stream of this host thread on ``dev`` (default
+    priority).  One per thread and device: the library keeps one workspace
+    per stream, and a library call's launches must not interleave with
+    another thread's on the same stream."""
+    streams = getattr(_SIDE, "streams", None)
+    if streams is None:
+        streams = _SIDE.streams = {}
+    s = streams.get(dev.index)
     if s is None:
-        s = _SIDE_STREAMS[dev.index] = torch.cuda.Stream(device=dev)
+        s = streams[dev.index] = torch.cuda.Stream(device=dev)
     return s
 
 

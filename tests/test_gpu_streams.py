@@ -92,3 +92,44 @@ def test_host_threads(nb):
         t.join(timeout=120)
     assert not any(t.is_alive() for t in threads)
     assert not errors, errors[:3]
+
+
+def test_checkpointed_gradient_from_host_threads(nb):
+    # the eager checkpointed leap-frog gradient recomputes positions on a
+    # second stream of its own thread: two threads, each on its own stream,
+    # must reproduce the single-thread gradient bitwise
+    dev = need_gpu()
+    n = 3000
+    x0 = to_dev(inputs.plummer_positions(n, (76, 0)), dev)
+    v0 = to_dev(inputs.plummer_velocities(inputs.plummer_positions(n, (76, 0)), (76, 1)), dev)
+    m0 = to_dev(inputs.lognormal_masses(n, (76, 2)), dev)
+    u = to_dev(inputs.normal((n, 3), (76, 3)), dev)
+
+    def grad():
+        x, v, m = (t.clone().requires_grad_(True) for t in (x0, v0, m0))
+        xT, _ = nb.leapfrog(x, v, m, 1e-4, 1e-3, 24, checkpoint_every=4, graphs=False)
+        return torch.autograd.grad((xT * u).sum(), (x, v, m))
+
+    ref = grad()
+    torch.cuda.synchronize()
+    errors = []
+
+    def work():
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    got = grad()
+                    s.synchronize()
+                    if not all(torch.equal(a, b) for a, b in zip(got, ref)):
+                        errors.append("mismatch")
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work) for _ in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors[:3]
