@@ -717,12 +717,17 @@ def main() -> int:
         lf_times = {}
         for graphs in (False, True):
             lf(graphs)                   # the first graphs call captures them
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                lf(graphs)
-            torch.cuda.synchronize()
-            lf_times[graphs] = (time.perf_counter() - t0) / 3
+        # both paths in alternation, best of five rounds of three calls, so
+        # that a drift of the clock during the leg favours neither
+        for _ in range(5):
+            for graphs in (False, True):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    lf(graphs)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / 3
+                lf_times[graphs] = min(lf_times.get(graphs, t), t)
         lf_s = lf_times[True]
         # forward: a(x0) and one force evaluation per step; reverse: every
         # segment but the last (whose positions the forward pass kept) is
