@@ -143,7 +143,8 @@ def _want(t: torch.Tensor, name: str, shape, device=None) -> None:
     # than in the library); anything else goes through the checks below,
     # which name what is wrong
     if (type(t) is torch.Tensor and t.is_cuda and t.dtype is _F32 and t.is_contiguous()
-            and t.shape == shape and (device is None or t.get_device() == device.index)):
+            and t.shape == shape
+            and (device is None or _ONE_DEVICE is True or t.get_device() == device.index)):
         return
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
@@ -179,7 +180,8 @@ def forces(x: torch.Tensor, m: torch.Tensor, eps2: float, *, out=None, potential
     potential is not stored and ``p`` is returned as None.  ``f64_sum`` keeps
     each row's running sum (over j-tiles and j-splits) in float64.
     """
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     dev = x.device
     _want(m, "m", (n,), dev)
@@ -207,7 +209,8 @@ def forces_noalloc(x: torch.Tensor, m: torch.Tensor, eps2: float, a: torch.Tenso
     allocates nothing for the call (its workspace is a fixed 64 MiB device
     region per device).  The caller supplies the outputs ``a`` [n,3] and,
     optionally, ``p`` [n]; calls that overlap in time on one device race."""
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     dev = x.device
     _want(m, "m", (n,), dev)
@@ -222,7 +225,8 @@ def forces_noalloc(x: torch.Tensor, m: torch.Tensor, eps2: float, a: torch.Tenso
 
 def forces_backward(x, m, eps2, grad_a=None, grad_p=None, *, need_grad_m: bool = True, out=None):
     """Vector-Jacobian product of :func:`forces`: (dL/dx [n,3], dL/dm [n] or None)."""
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     dev = x.device
     _want(m, "m", (n,), dev)
@@ -261,7 +265,8 @@ def forces_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float, *, ou
     ``offsets`` is a host array (numpy, list or CPU tensor) of int64.
     """
     o = _offsets_array(offsets)
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     dev = x.device
     _want(m, "m", (n,), dev)
@@ -292,7 +297,8 @@ def axpy_(y: torch.Tensor, xv: torch.Tensor, alpha: float) -> torch.Tensor:
 
 def kick_drift_(x: torch.Tensor, v: torch.Tensor, a: torch.Tensor, kick: float, dt: float):
     """In place v += kick * a, then x += dt * v (one leap-frog kick + drift)."""
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     _want(v, "v", (n, 3), x.device)
     _want(a, "a", (n, 3), x.device)
@@ -407,7 +413,8 @@ def autotune_batched(x: torch.Tensor, m: torch.Tensor, offsets, eps2: float) -> 
     """Time every batched variant on this ensemble, keep the fastest for its
     mean system size, and return that variant's index."""
     o = _offsets_array(offsets)
-    n = int(x.shape[0]) if x.dim() == 2 else -1
+    sh = x.shape
+    n = sh[0] if len(sh) == 2 else -1
     _want(x, "x", (n, 3))
     _want(m, "m", (n,), x.device)
     if int(o[-1]) != n:
