@@ -187,7 +187,7 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
  * Kernels: for 4,800 <= n <= 2^24 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair),
- * for blocks of P = 1024 particles from 2^18, 512 from 2^16 and 128 or 256
+ * for blocks of P = 1024 particles from 2^18, 512 from 40,000 and 128
  * below, with the ring groups and bounded workspace of
  * the pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it does not form the
  * potential-weight terms (with the same variant, bitwise the result of zero

@@ -794,7 +794,6 @@ int backward_default_variant(int64_t n, bool has_v)
 {
     static const int pair_once_big = variant_index("bwd_sym_w8_k2_r8");
     static const int pair_once_large = variant_index("bwd_sym_w4_k2_r8");
-    static const int pair_once_mid = variant_index("bwd_sym_w2_k2_o1");
     static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
     static const int pair_once_r8_small = variant_index("bwd_sym_w2_k1_r8");
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
@@ -802,23 +801,20 @@ int backward_default_variant(int64_t n, bool has_v)
     static const int row_1 = variant_index("bwd_row_k1");
     static const int row_2 = variant_index("bwd_row_k2");
     if (n > (1 << 24)) return gather;
-    // eight rounds of one-wave workgroups (down to one tile each, which the
-    // dispatcher hands out as slots free up): 4-9% faster than one round
-    // without potential weights from 9,000 to 2^17 bodies and 3-5% with them
-    // from 10,000 to 24,575 (interleaved A/B); 16% for two-wave one-row
-    // blocks at 6,000 without them.  A forced-variant sweep at 8,192 bodies
-    // put the one-wave two-row blocks 4% ahead of those without potential
-    // weights, and the two-wave one-row blocks in eight rounds 6% ahead of
-    // one round with them.
-    // From 2^16 eight rounds of 4- and 8-wave blocks (forced-variant sweep,
-    // same box): 9-11% ahead of one round of 8-wave blocks at 2^17, 4-6% at
-    // 2^18, 3-7% at 2^19, with and without potential weights.
+    // Eight rounds of workgroups (each block's tiles cut into eight times as
+    // many chunks as the device holds workgroups, down to one tile; the
+    // dispatcher hands the short ones out as slots free up) lead from 6,000
+    // bodies up in forced-variant sweeps on one box: two-wave one-row blocks
+    // below 8,000 (10,000 with potential weights; 6% ahead of one round at
+    // 8,192), then one-wave two-row blocks (4-9% ahead of one round up to
+    // 2^17), 4-wave blocks from 40,000 (10-13% ahead of one round of
+    // two-wave blocks with potential weights at 49,152 and 60,000, 9-11% of
+    // 8-wave ones at 2^17) and 8-wave blocks from 2^18 (3-7% ahead of one
+    // round of them at 2^18 and 2^19).
     if (n >= (1 << 18)) return pair_once_big;
-    if (n >= (1 << 16)) return pair_once_large;
-    if (!has_v && n >= 8000) return pair_once_r8;
-    if (n >= 6000 && n < (has_v ? 10000 : 8000)) return pair_once_r8_small;
-    if (has_v && n >= 10000 && n < 24576) return pair_once_r8;
-    if (has_v && n >= 24576) return pair_once_mid;
+    if (n >= 40000) return pair_once_large;
+    if (n >= (has_v ? 10000 : 8000)) return pair_once_r8;
+    if (n >= 6000) return pair_once_r8_small;
     // one wave per row below 4,800 bodies (two rows from 3,500): 4.7 against
     // 16.1 us per call at 1,024 (split gather and its reduction), 18.3
     // against 21.8 at 4,096 (pair-once and its fold), 34.5 against 29.3 at
