@@ -133,3 +133,49 @@ def test_running_sum_is_aligned(L, n, monkeypatch):
     for name in ("fwd_sym_w8_k4_o1", "fwd_sym_w1_k2_r8"):
         b, _ = plan(L, 0, name, n, 2)
         assert b > 0 and (b - 32 * n) % 256 == 0 and b % 256 != 0, (name, n, b)
+
+
+DEFAULTS_CHILD = r"""
+import ctypes, json, sys
+L = ctypes.CDLL(sys.argv[1])
+L.nbody_variant_name.restype = ctypes.c_char_p
+L.nbody_selected_variant.argtypes = [ctypes.c_int, ctypes.c_int64]
+out = {}
+for kind in (0, 1):
+    for n in [int(a) for a in sys.argv[2:]]:
+        v = L.nbody_selected_variant(kind, n)
+        out[f"{kind}:{n}"] = L.nbody_variant_name(kind, v).decode()
+print(json.dumps(out))
+"""
+
+
+def test_default_table(tmp_path):
+    # the default kernel by size (no tuning cache, nothing forced), as the
+    # header and the measured crossovers give it; host code only
+    import json
+    import subprocess
+    import sys
+    if not os.path.exists(B.LIBRARY):
+        pytest.skip("libnbody.so not built (run __graft_entry__.build())")
+    sizes = [1024, 2999, 3000, 4096, 4800, 5499, 5500, 6000, 8000, 9999, 10000, 12000,
+             20000, 40000, 65536, 1 << 18, 1 << 20, 1 << 24, (1 << 24) + 1]
+    env = dict(os.environ, NBODY_TUNE_CACHE=str(tmp_path / "none.json"))
+    env.pop("NBODY_VARIANT", None)
+    r = subprocess.run([sys.executable, "-c", DEFAULTS_CHILD, B.LIBRARY, *map(str, sizes)],
+                       env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    fwd = {1024: "fwd_row_k1", 2999: "fwd_row_k1", 3000: "fwd_row_k2", 4096: "fwd_row_k2",
+           5499: "fwd_row_k2", 5500: "fwd_sym_w1_k2_o1", 10000: "fwd_sym_w1_k2_o1",
+           12000: "fwd_sym_w1_k2_r8", 20000: "fwd_sym_w1_k4_r8", 40000: "fwd_sym_w1_k4_r8",
+           65536: "fwd_sym_w4_k4_r8", 1 << 18: "fwd_sym_w4_k4_r8", 1 << 20: "fwd_sym_w8_k4_r8",
+           1 << 24: "fwd_sym_w8_k4_r8", (1 << 24) + 1: "fwd_b64_k1_u8_f64sum"}
+    # the adjoint with potential weights (nbody_selected_variant's choice)
+    bwd = {1024: "bwd_row_k1", 3000: "bwd_row_k1", 4096: "bwd_row_k2", 4800: "bwd_sym_w2_k1_o1",
+           6000: "bwd_sym_w2_k1_r8", 9999: "bwd_sym_w2_k1_r8", 10000: "bwd_sym_w1_k2_r8",
+           20000: "bwd_sym_w1_k2_r8", 40000: "bwd_sym_w4_k2_r8", 65536: "bwd_sym_w4_k2_r8",
+           1 << 18: "bwd_sym_w8_k2_r8", 1 << 24: "bwd_sym_w8_k2_r8",
+           (1 << 24) + 1: "bwd_b256_k1_u8"}
+    for kind, table in ((0, fwd), (1, bwd)):
+        for n, name in table.items():
+            assert got[f"{kind}:{n}"] == name, (kind, n, got[f"{kind}:{n}"])
