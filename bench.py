@@ -468,6 +468,12 @@ def latency_leg(nb, torch, dev, inputs, held=None, reps: int = 2000):
                      "kernels_us": cm * 1e3,
                      "variant": nb.variant_names(k)[nb.selected_variant(k, w.n)]}
         log(f"{kind} N = 1,024: {wall * 1e6 / reps:.2f} us per call, kernel {km * 1e3:.2f} us")
+    # the same forward through a prepared call (tensors checked once)
+    bound = nb.BoundForces(x, m, w.eps2, a, p)
+    warm_up(bound, torch)
+    wall, _, _ = timed_calls(bound, reps, torch, nb)
+    rec["forward"]["us_per_call_bound"] = wall * 1e6 / reps
+    log(f"forward N = 1,024 through BoundForces: {wall * 1e6 / reps:.2f} us per call")
     if held is not None:
         torch.cuda.synchronize()
         held["adjoint_1k"] = (w, gx.cpu().numpy().astype(np.float64),

@@ -25,6 +25,7 @@ def test_host_tensors_are_refused():
         lambda: nb.kick_drift_(x, v, a, -0.5e-3, 1e-3),
         lambda: nb.leapfrog_(x, v, a, m, 1e-4, 1e-3, 2),
         lambda: nb.leapfrog_adjoint_(torch.zeros((3, 4, 3)), m, 1e-4, 1e-3, x, v, m.clone()),
+        lambda: nb.BoundForces(x, m, 1e-4, a),
     ]
     for call in calls:
         with pytest.raises(ValueError, match="HIP device"):

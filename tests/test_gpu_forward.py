@@ -318,6 +318,28 @@ def test_row_per_wave(nb, n):
         nb.set_variant(nb.FORWARD, -1)
 
 
+@pytest.mark.parametrize("n", [1024, 20000])
+def test_bound_forces(nb, n):
+    # the prepared call gives the bits of forces(); new values written into
+    # the bound x are picked up by the next call
+    dev = need_gpu()
+    x = to_dev(inputs.plummer_positions(n, (69, n)), dev)
+    m = to_dev(inputs.lognormal_masses(n, (69, n, 1)), dev)
+    a = torch.empty((n, 3), device=dev)
+    p = torch.empty((n,), device=dev)
+    a_only = torch.empty((n, 3), device=dev)
+    call, call_a = nb.BoundForces(x, m, 1e-4, a, p), nb.BoundForces(x, m, 1e-4, a_only)
+    for step in range(2):
+        call()
+        call_a()
+        a_ref, p_ref = nb.forces(x, m, 1e-4)
+        torch.cuda.synchronize()
+        assert torch.equal(a, a_ref) and torch.equal(p, p_ref) and torch.equal(a_only, a_ref), step
+        x.mul_(1.5)                        # the same storage, new values
+    with pytest.raises(ValueError):
+        nb.BoundForces(x, m[:-1], 1e-4, a)
+
+
 def test_four_million(nb):
     # n = 2^22: the default pair-once kernel runs its ring in groups of
     # offsets (bounded workspace) with float64 running sums between groups;
