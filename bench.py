@@ -734,12 +734,18 @@ def main() -> int:
                 torch.cuda.synchronize()
                 t = (time.perf_counter() - t0) / 3
                 lf_times[graphs] = min(lf_times.get(graphs, t), t)
-        lf_s = lf_times[True]
-        # forward: a(x0) and one force evaluation per step; reverse: every
-        # segment but the last (whose positions the forward pass kept) is
-        # recomputed from its checkpoint (x, v, a): 7 x 8 evaluations
-        f_evals = 1 + 64 + 7 * 8
+        from paper_0904_3659_amd import leapfrog as LF
+        lf_default = wa.n <= LF.GRAPHS_MAX_N     # what graphs=None takes
+        lf_s = lf_times[lf_default]
+        # forward: a(x0) and one force evaluation per step; reverse: the
+        # positions inside every segment but the last (whose positions the
+        # forward pass kept) are recomputed from its checkpoint (x, v, a),
+        # 8 - 2 evaluations each (the end is the next checkpoint, the step
+        # before it needs only a kick and a drift): 7 x 6 evaluations
+        f_evals = 1 + 64 + 7 * 6
         out["leapfrog_grad"] = {"workload": wa.name + "_64steps_dt1e-3_ckpt8", "seconds": lf_s,
+                                "graphs_by_default": lf_default,
+                                "seconds_with_graphs": lf_times[True],
                                 "seconds_without_graphs": lf_times[False],
                                 "force_evals": f_evals, "vjp_evals": 64,
                                 "pairs_per_s": (f_evals + 64) * metrics.pairs(wa.n) / lf_s}

@@ -20,10 +20,13 @@ same positions with the same weight, so they are applied as one product with
 factor dt.  Masses collect the same products' dL/dm parts.
 
 Checkpointing: the forward pass keeps (x, v) every ``checkpoint_every``
-steps; the reverse pass recomputes each segment's positions from its
-checkpoint before sweeping it.  The kernels are deterministic, so the
-recomputed positions and hence the gradients are bitwise equal to those of a
-run that stores every position.
+steps; the reverse pass recomputes the positions inside each segment from
+its checkpoint before sweeping it.  A k-step segment needs k - 2 force
+evaluations for that: its end position is the next checkpoint, and the
+position before the end takes only the start kick and drift of the last
+step, so the forces at those two positions are never recomputed.  The
+kernels are deterministic, so the recomputed positions and hence the
+gradients are bitwise equal to those of a run that stores every position.
 
 HIP graphs: a k-step segment (2k + 1 launches), the recomputation of a
 segment's positions and the reverse sweep over an interior segment are each
@@ -81,12 +84,20 @@ def integrate(x0, v0, m, eps2, dt, steps, *, keep_every: int | None = None):
     return x, v, saved
 
 
-def _positions(xs, vs, a0, m, eps2, dt, count):
+def _positions(xs, vs, a0, x_end, m, eps2, dt, count):
     """Positions [count + 1, n, 3] after 0..count steps from (xs, vs) with
-    a0 = a(xs)."""
+    a0 = a(xs), given x_end, the positions after the last step: count - 2
+    full steps, then the start kick and drift of the next one (bitwise the
+    fused step, as nbody_leapfrog is bitwise its composed calls)."""
     pos = torch.empty((count + 1,) + tuple(xs.shape), dtype=xs.dtype, device=xs.device)
     pos[0].copy_(xs)
-    _nb.leapfrog_(xs.clone(), vs.clone(), a0.clone(), m, eps2, dt, count, x_hist=pos[1:])
+    pos[count].copy_(x_end)
+    if count >= 2:
+        x, v, a = xs.clone(), vs.clone(), a0.clone()
+        if count > 2:
+            _nb.leapfrog_(x, v, a, m, eps2, dt, count - 2, x_hist=pos[1:count - 1])
+        pos[count - 1].copy_(x)
+        _nb.kick_drift_(pos[count - 1], v, a, -0.5 * dt, dt)
     return pos
 
 
@@ -143,7 +154,7 @@ def reverse_sweep(saved, m, eps2, dt, steps, gx_T, gv_T, checkpoint_every):
         s0 = rec[i]
         xs, vs, a0 = saved[s0]
         with torch.cuda.stream(side):
-            pos = _positions(xs, vs, a0, m, eps2, dt, min(k, steps - s0))
+            pos = _positions(xs, vs, a0, saved[s0 + k][0], m, eps2, dt, k)
             ev = torch.cuda.Event()
             ev.record(side)
         pos.record_stream(main)
@@ -168,8 +179,9 @@ class SegmentGraphs:
     """HIP graphs over fixed buffers for one (m, eps2, dt, k):
 
     ``fwd``     k steps on (x, v, a), with a = a(x) on entry and exit;
-    ``pos<b>``  k steps from (pos[b][0], pv[b], pa[b]), keeping
-                pos[b][1..k], for position buffers b = 0, 1;
+    ``pos<b>``  pos[b][1..k-1] from (pos[b][0], pv[b], pa[b]): k - 2 steps,
+                then the start kick and drift of the next, for position
+                buffers b = 0, 1 (pos[b][k] is the next checkpoint);
     ``rev<b>``  the reverse sweep over an interior segment (global step > 0)
                 with positions pos[b][0..k].
 
@@ -204,9 +216,13 @@ class SegmentGraphs:
         _nb.leapfrog_(self.x, self.v, self.a, self.m, self.eps2, self.dt, self.k)
 
     def _pos(self, b: int):
-        self.px[b].copy_(self.pos[b][0])
-        _nb.leapfrog_(self.px[b], self.pv[b], self.pa[b], self.m, self.eps2, self.dt, self.k,
-                      x_hist=self.pos[b][1:])
+        k, P = self.k, self.pos[b]
+        if k > 2:
+            self.px[b].copy_(P[0])
+            _nb.leapfrog_(self.px[b], self.pv[b], self.pa[b], self.m, self.eps2, self.dt, k - 2,
+                          x_hist=P[1:k - 1])
+        P[k - 1].copy_(P[k - 2])
+        _nb.kick_drift_(P[k - 1], self.pv[b], self.pa[b], -0.5 * self.dt, self.dt)
 
     def _rev(self, b: int):
         _nb.leapfrog_adjoint_(self.pos[b], self.m, self.eps2, self.dt, self.lx, self.lv, self.lm)
@@ -226,10 +242,11 @@ class SegmentGraphs:
     def replay(self, name: str):
         self._graphs[name][0].replay()
 
-    def segment_positions(self, b: int, xs, vs, a0):
-        """pos[b][0..k] from (xs, vs, a0 = a(xs)) by one replay on the
-        current stream; (pv[b], pa[b]) then hold (v, a) after the k steps."""
+    def segment_positions(self, b: int, xs, vs, a0, x_end):
+        """pos[b][0..k] of the k steps from (xs, vs, a0 = a(xs)) that end at
+        x_end, by one replay on the current stream."""
         self.pos[b][0].copy_(xs)
+        self.pos[b][self.k].copy_(x_end)
         self.pv[b].copy_(vs)
         self.pa[b].copy_(a0)
         self.replay(f"pos{b}")
@@ -265,13 +282,7 @@ def integrate_graphs(G: SegmentGraphs, x0, v0, steps: int):
         saved[t] = (G.x.clone(), G.v.clone(), G.a.clone())
         if t < last:
             G.replay("fwd")
-        elif steps - t == k:                 # a full last segment: keep its positions
-            pos = G.segment_positions(0, G.x, G.v, G.a)
-            saved["tail"] = pos.clone()
-            G.x.copy_(pos[k])
-            G.v.copy_(G.pv[0])
-            G.a.copy_(G.pa[0])
-        else:
+        else:                                # the last segment: keep its positions
             count = steps - t
             tail = torch.empty((count + 1,) + tuple(G.x.shape), dtype=G.x.dtype, device=G.x.device)
             tail[0].copy_(G.x)
@@ -318,7 +329,7 @@ def reverse_sweep_graphs(G: SegmentGraphs, saved, steps, gx_T, gv_T):
         with torch.cuda.stream(side):
             if freed[b] is not None:
                 side.wait_event(freed[b])         # the sweep that last read buffer b
-            G.segment_positions(b, *saved[s0])
+            G.segment_positions(b, *saved[s0], saved[s0 + k][0])
             ready[s0] = torch.cuda.Event()
             ready[s0].record(side)
 
@@ -355,6 +366,8 @@ class Leapfrog(torch.autograd.Function):
         if k < 1:
             raise ValueError("checkpoint_every must be >= 1")
         md = m.detach()
+        if graphs is None:
+            graphs = md.shape[0] <= GRAPHS_MAX_N
         G = segment_graphs(md, eps2, dt, k) if graphs and k > 1 and steps >= k else None
         if G is not None:
             x, v, saved = integrate_graphs(G, x0.detach(), v0.detach(), int(steps))
@@ -377,14 +390,27 @@ class Leapfrog(torch.autograd.Function):
         return lx, lv, lm, None, None, None, None, None
 
 
+# Largest n for which ``leapfrog(graphs=None)`` replays HIP graphs.  The
+# 64-step gradient with checkpoints every 8 steps takes 11-19% less time
+# with graphs from 128 to 2,048 bodies, where a step's kernels take a few
+# microseconds and the host's launches show; from 3,000 bodies on the
+# eager launches are faster (5% at 3,000, 18% at 4,096, 3% at 16,384): a
+# graph's kernel nodes start a little later than launches into a stream,
+# and the eager reverse pass recomputes positions as far ahead of the sweep
+# as the host gets (a tensor per segment) where the graphs have two fixed
+# position buffers.
+GRAPHS_MAX_N = 2048
+
+
 def leapfrog(x0, v0, m, eps2: float, dt: float, steps: int, checkpoint_every: int | None = 8,
-             graphs: bool = True):
+             graphs: bool | None = None):
     """Integrate ``steps`` leap-frog steps; differentiable in (x0, v0, m).
 
     ``checkpoint_every=k`` keeps (x, v) every k steps and recomputes the
     rest in the backward pass; ``None`` or 1 keeps every step.  With
     ``graphs`` (and k > 1) the segments replay from cached HIP graphs
     (``SegmentGraphs``); the result is bitwise that of ``graphs=False``.
-    The graphs read ``m`` in place at every replay.
+    ``None`` takes graphs for n <= ``GRAPHS_MAX_N``.  The graphs read ``m``
+    in place at every replay.
     """
     return Leapfrog.apply(x0, v0, m, eps2, dt, steps, checkpoint_every, graphs)

@@ -27,11 +27,11 @@ def _case(n, seed):
     return x, v, m, u
 
 
-def _grads(nb, x, v, m, u, eps2, dt, steps, k, dev):
+def _grads(nb, x, v, m, u, eps2, dt, steps, k, dev, graphs=True):
     xt = to_dev(x, dev).requires_grad_(True)
     vt = to_dev(v, dev).requires_grad_(True)
     mt = to_dev(m, dev).requires_grad_(True)
-    xT, vT = nb.leapfrog(xt, vt, mt, eps2, dt, steps, checkpoint_every=k)
+    xT, vT = nb.leapfrog(xt, vt, mt, eps2, dt, steps, checkpoint_every=k, graphs=graphs)
     loss = (xT * to_dev(u, dev)).sum()
     gx, gv, gm = torch.autograd.grad(loss, (xt, vt, mt))
     torch.cuda.synchronize()
@@ -47,14 +47,21 @@ def test_trajectory_matches_oracle(nb):
     assert err <= 1e-5 * np.abs(rx).max()
 
 
-def test_checkpointing_is_bitwise_neutral(nb):
+@pytest.mark.parametrize("n,steps,ks", [(2048, 64, (8, 5, 64, 3, 2)), (9000, 12, (4, 3, 2))])
+def test_checkpointing_is_bitwise_neutral(nb, n, steps, ks):
+    # The reverse pass recomputes k - 2 full steps of each segment, then a
+    # kick and a drift, and takes the segment's end from the next
+    # checkpoint: k = 2 and 3 are the edges of that; 2,048 bodies run the
+    # row-per-wave kernels, 9,000 the pair-once ones.
     dev = need_gpu()
-    x, v, m, u = _case(2048, 1)
-    ref = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 1, dev)
-    for k in (8, 5, 64):
-        got = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, k, dev)
-        for a, b in zip(ref, got):
-            assert torch.equal(a, b), f"checkpoint_every={k}"
+    x, v, m, u = _case(n, 1)
+    print(f"[checkpointing] n={n} steps={steps} k={ks}", flush=True)
+    ref = _grads(nb, x, v, m, u, 1e-4, 1e-3, steps, 1, dev)
+    for k in ks:
+        for graphs in (True, False):
+            got = _grads(nb, x, v, m, u, 1e-4, 1e-3, steps, k, dev, graphs)
+            for a, b in zip(ref, got):
+                assert torch.equal(a, b), f"checkpoint_every={k} graphs={graphs}"
 
 
 def test_gradient_matches_oracle_sweep(nb):
@@ -108,6 +115,21 @@ def test_full_config_against_oracle(nb):
     an = float(np.sum(host(gx) * d))
     print(f"[parity] leapfrog 16k directional: GPU {an:.8e} FD {fd:.8e}", flush=True)
     assert an == pytest.approx(fd, rel=1e-3)
+
+
+def test_graphs_by_default_only_for_small_n(nb):
+    # graphs=None replays HIP graphs up to GRAPHS_MAX_N bodies, eager above
+    from paper_0904_3659_amd import leapfrog as LF
+    dev = need_gpu()
+    for n, want in ((LF.GRAPHS_MAX_N, True), (LF.GRAPHS_MAX_N + 1, False)):
+        x, v, m, u = _case(n, 7)
+        LF._GRAPH_CACHE.clear()
+        xt, vt, mt = (to_dev(t, dev).requires_grad_(True) for t in (x, v, m))
+        xT, _ = nb.leapfrog(xt, vt, mt, 1e-4, 1e-3, 16, checkpoint_every=4)
+        (xT * to_dev(u, dev)).sum().backward()
+        torch.cuda.synchronize()
+        assert bool(LF._GRAPH_CACHE) == want, n
+    LF._GRAPH_CACHE.clear()
 
 
 def test_resume_from_checkpoint_is_bitwise(nb):
