@@ -188,10 +188,11 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * Kernels: for 4,800 <= n <= 2^24 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair),
  * for blocks of P = 1024 particles from 2^18, 512 from 40,000 and 128
- * below, with the ring groups and bounded workspace of
- * the pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it does not form the
- * potential-weight terms (with the same variant, bitwise the result of zero
- * weights) and the default may take other block shapes.  Below 4,800 one
+ * below (from 6,000 to 11,999 two waves share a block's rows and split
+ * each tile's steps), with the ring groups and bounded workspace of the
+ * pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it
+ * does not form the potential-weight terms (with the same variant, bitwise
+ * the result of zero weights); the default variant is the same.  Below 4,800 one
  * launch with one wave per row (two rows from 3,500) evaluates every
  * ordered pair (no workspace); above 2^24 every ordered pair is gathered
  * per row.
@@ -371,8 +372,8 @@ int64_t nbody_variant_plan(int kind, int index, int64_t n, int num_cu, int block
 
 /*
  * Variant index the library would use for `kind` at size n (-1 on error);
- * for NBODY_KIND_BACKWARD the choice for a call with grad_p given (without
- * it, and in nbody_leapfrog_adjoint, the default can differ).
+ * for NBODY_KIND_BACKWARD the same with and without grad_p and in
+ * nbody_leapfrog_adjoint.
  */
 int nbody_selected_variant(int kind, int64_t n);
 

@@ -443,21 +443,21 @@ __device__ __forceinline__ void load_xw(const SymBwdArgs &A, int j, float4 &xm, 
     }
 }
 
-// The 64 steps of one tile for one wave (lane l meets tile particle
-// (l + s) mod 64 at step s).  Ring tiles: every row tile pair-once.
+// Steps s0 .. s0 + NS - 1 of one tile for one wave (lane l meets tile
+// particle (l + s) mod 64 at step s).  Ring tiles: every row tile pair-once.
 // Diagonal tile t: row tile a = a0 + k pair-once if a < t, masked ordered
 // pairs if a == t, nothing if a > t (met on diagonal tile a).
-template <int K, bool DIAG>
+template <int K, bool DIAG, int NS = 64>
 __device__ __forceinline__ void adj_tile_steps(const float4 (&xk)[K], const float4 (&wk)[K],
                                                const int (&kk)[K], const float4 *tile_xm,
                                                const float4 *tile_wv, float4 *slot, int lane,
-                                               int a0, int t, int jbase, float eps2,
+                                               int a0, int t, int jbase, int s0, float eps2,
                                                float4 (&tk)[K])
 {
     const bool any_once = !DIAG || a0 < t;
-    float4 q = tile_xm[lane];
-    float4 wq = tile_wv[lane];
-    for (int s = 0; s < 64; ++s) {
+    float4 q = tile_xm[(lane + s0) & 63];
+    float4 wq = tile_wv[(lane + s0) & 63];
+    for (int s = s0; s < s0 + NS; ++s) {
         const int jj = (lane + s) & 63;
         // keep this step's slot read after the previous step's write
         __asm__ volatile("" ::: "memory");
@@ -489,20 +489,22 @@ __device__ __forceinline__ void adj_tile_steps(const float4 (&xk)[K], const floa
 // reads entry l + s and updates slot l + s with no index wrap (immediate
 // LDS offsets in the unrolled loop); particle e's j-side sum is slot e plus
 // slot e + 64, folded into slot e at the end.  Same scheme and ordering
-// argument as the forward pair-once kernel.
-template <int K, bool HAS_V = true>
+// argument as the forward pair-once kernel.  The wave takes steps
+// s0 .. s0 + NS - 1 (all 64 unless a tile's steps are split between waves;
+// s0 + NS <= 64 keeps every entry and slot below 128).
+template <int K, bool HAS_V = true, int NS = 64>
 __device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const float4 (&wk)[K],
                                                const float4 *tile_xm, const float4 *tile_wv,
-                                               float4 *slot, int lane, float eps2,
+                                               float4 *slot, int lane, int s0, float eps2,
                                                float4 (&tk)[K])
 {
-    const float4 *txm = tile_xm + lane;
-    const float4 *twv = tile_wv + lane;
-    float4 *sl = slot + lane;
+    const float4 *txm = tile_xm + lane + s0;
+    const float4 *twv = tile_wv + lane + s0;
+    float4 *sl = slot + lane + s0;
     float4 q = txm[0];
     float4 wq = twv[0];
 #pragma unroll 4
-    for (int s = 0; s < 64; ++s) {
+    for (int s = 0; s < NS; ++s) {
         // keep this step's slot read after the previous step's write
         __asm__ volatile("" ::: "memory");
         float4 ja = sl[s];
@@ -522,11 +524,17 @@ __device__ __forceinline__ void adj_ring_steps(const float4 (&xk)[K], const floa
 
 // HAS_V false: no potential weights (grad_p NULL); their terms are not
 // formed on ring tiles (bitwise the same result as v = 0).
-template <int W, int K, bool HAS_V>
+// S = 1: each wave owns K * 64 of the block's rows.  S = W > 1: the W waves
+// share the block's K * 64 rows and each takes 64 / W of every tile's steps
+// (workgroups W times shorter for the same block size, so the grid's drain
+// is shorter); their row sums are added in wave order at the end.
+template <int W, int K, bool HAS_V, int S = 1>
 __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
 {
-    constexpr int PB = W * 64 * K;
+    static_assert(S == 1 || (S == W && K <= 2), "a step split spans all waves, two rows at most");
+    constexpr int PB = (S > 1 ? 64 : W * 64) * K;
     constexpr int TPB = PB / 64;
+    constexpr int NS = 64 / S;
     __shared__ float4 tile_xm[128];
     __shared__ float4 tile_wv[128];
     __shared__ float4 jacc[W][128];
@@ -539,12 +547,14 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
     const int I = blockIdx.x / C;
     const int c = blockIdx.x - I * C;
     const float eps2 = A.eps2;
+    const int wrow = S > 1 ? 0 : wv;      // this wave's row group
+    const int s0 = S > 1 ? wv * NS : 0;   // and first step of each tile
 
     float4 xk[K], wk[K], acc[K];
     int kk[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int i = I * PB + wv * 64 * K + k * 64 + lane;
+        const int i = I * PB + wrow * 64 * K + k * 64 + lane;
         kk[k] = i;
         if (i < n) {
             load_xw(A, i, xk[k], wk[k]);
@@ -591,10 +601,10 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
         float4 *slot = &jacc[wv][0];
         const bool diag = (cur_delta == 0);
         if (!diag)
-            adj_ring_steps<K, HAS_V>(xk, wk, tile_xm, tile_wv, slot, lane, eps2, tk);
+            adj_ring_steps<K, HAS_V, NS>(xk, wk, tile_xm, tile_wv, slot, lane, s0, eps2, tk);
         else
-            adj_tile_steps<K, true>(xk, wk, kk, tile_xm, tile_wv, slot, lane, wv * K, cur_u,
-                                    cur_base, eps2, tk);
+            adj_tile_steps<K, true, NS>(xk, wk, kk, tile_xm, tile_wv, slot, lane, wrow * K,
+                                        cur_u, cur_base, s0, eps2, tk);
         __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -618,9 +628,10 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                 const int j = cur_base + tid;
                 if (j < n) A.partial[(size_t)(C + cur_delta - dj) * n + j] = sum;
             }
-        } else if (wv == cur_u / K) {
-            // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K);
-            // the diagonal steps use slots 0..63 only
+        } else if (wv == (S > 1 ? 0 : cur_u / K)) {
+            // this wave holds diagonal tile cur_u's rows (lane-slot cur_u % K;
+            // with a step split every wave does, and wave 0 adds); the
+            // diagonal steps use slots 0..63 only
             float4 sum = jacc[0][lane];
 #pragma unroll
             for (int w2 = 1; w2 < W; ++w2) {
@@ -630,7 +641,7 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                 sum.z += v.z;
                 sum.w += v.w;
             }
-            const int kt = cur_u - wv * K;
+            const int kt = cur_u - wrow * K;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (k == kt) {
@@ -641,23 +652,44 @@ __global__ __launch_bounds__(W * 64) void backward_sym_kernel(SymBwdArgs A)
                 }
         }
     }
+    if (S > 1) {
+        // the waves' row sums, added in wave order by wave 0 (through the
+        // j-side slots, which the last tile's reads are done with)
+        __syncthreads();
+        if (wv > 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) jacc[wv][k * 64 + lane] = acc[k];
+        }
+        __syncthreads();
+        if (wv > 0) return;
+#pragma unroll
+        for (int w2 = 1; w2 < W; ++w2)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float4 v = jacc[w2][k * 64 + lane];
+                acc[k].x += v.x;
+                acc[k].y += v.y;
+                acc[k].z += v.z;
+                acc[k].w += v.w;
+            }
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (kk[k] < n) A.partial[(size_t)c * n + kk[k]] = acc[k];
 }
 
 // OCC divides the chunk count and ROUNDS multiplies it (as in the
-// pair-once forward kernel).
-template <int W, int K, int OCC, int ROUNDS = 1>
+// pair-once forward kernel); S splits each tile's steps between the waves.
+template <int W, int K, int OCC, int ROUNDS = 1, int S = 1>
 nbody_status run_backward_sym(const char *name, const Device &dev, const float *x, const float *m,
                               int n, float eps2, const float *ga, const float *gp, float *gx,
                               float *gm, hipStream_t stream, const LfEpi *epi, bool *fused,
                               const Arena &arena)
 {
-    constexpr int PB = W * 64 * K;
+    constexpr int PB = (S > 1 ? 64 : W * 64) * K;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, backward_sym_kernel<W, K, true>, W * 64, 0);
+        &per_cu, backward_sym_kernel<W, K, true, S>, W * 64, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
     SymPlan pl;
@@ -679,11 +711,11 @@ nbody_status run_backward_sym(const char *name, const Device &dev, const float *
         sym_group(pl, g, &A.d_lo, &A.d_hi);
         prof_mark(stream, 0);
         if (gp)
-            hipLaunchKernelGGL((backward_sym_kernel<W, K, true>), dim3(pl.M * pl.C), dim3(W * 64), 0,
-                               stream, A);
+            hipLaunchKernelGGL((backward_sym_kernel<W, K, true, S>), dim3(pl.M * pl.C),
+                               dim3(W * 64), 0, stream, A);
         else
-            hipLaunchKernelGGL((backward_sym_kernel<W, K, false>), dim3(pl.M * pl.C), dim3(W * 64),
-                               0, stream, A);
+            hipLaunchKernelGGL((backward_sym_kernel<W, K, false, S>), dim3(pl.M * pl.C),
+                               dim3(W * 64), 0, stream, A);
         prof_mark(stream, 1);
         st = check_launch(name);
         if (st != NBODY_OK) return st;
@@ -722,7 +754,14 @@ struct Variant {
     int sym_w, sym_k, sym_occ, sym_rounds;
     KernelFn row;  // row-per-wave kernel (K = row_k rows per wave)
     int row_k;
+    int sym_split;  // pair-once: waves sharing a block's rows (0 or 1: none)
 };
+
+// Particles per pair-once block of a variant.
+int sym_block(const Variant &V)
+{
+    return V.sym_w * 64 * V.sym_k / (V.sym_split > 1 ? V.sym_split : 1);
+}
 
 #define BWD_VARIANT(B, K, U) \
     {"bwd_b" #B "_k" #K "_u" #U, B, K, U, backward_kernel<B, K, U, false>, backward_kernel<B, K, U, true>, nullptr, nullptr, 0, 0, 0, 1}
@@ -733,6 +772,12 @@ struct Variant {
 #define BWD_SYM_R_VARIANT(W, K, R) \
     {"bwd_sym_w" #W "_k" #K "_r" #R, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, 1, R>, \
      backward_sym_kernel<W, K, true>, W, K, 1, R}
+
+// Pair-once blocks of K * 64 rows whose W waves split each tile's steps, in
+// R rounds of workgroups.
+#define BWD_SYM_S_VARIANT(W, K, R) \
+    {"bwd_sym_s" #W "_k" #K "_r" #R, 0, 0, 0, nullptr, nullptr, run_backward_sym<W, K, 1, R, W>, \
+     backward_sym_kernel<W, K, true, W>, W, K, 1, R, nullptr, 0, W}
 
 #define BWD_ROW_VARIANT(K) \
     {"bwd_row_k" #K, 64, K, 0, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 1, backward_row_kernel<K>, K}
@@ -763,6 +808,9 @@ const Variant kVariants[] = {
     BWD_SYM_R_VARIANT(4, 2, 8),
     BWD_ROW_VARIANT(1),
     BWD_ROW_VARIANT(2),
+    BWD_SYM_S_VARIANT(2, 2, 8),
+    BWD_SYM_S_VARIANT(2, 2, 16),
+    BWD_SYM_R_VARIANT(1, 2, 16),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -783,19 +831,16 @@ static int variant_index(const char *name)
 }
 
 // Measured on MI355X: the pair-once adjoint wins from about 4,800 particles
-// on, one wave per row below; its
-// workspace is bounded as the forward's (ring groups), and above 2^24
-// particles the gather kernel takes over.  Without potential weights
-// (grad_p NULL) each pair costs fewer registers and one-wave blocks of 128
-// particles lead from about 6,000 to 2^17 particles (5-12% ahead of the
-// two- and eight-wave blocks at 16,384 to 65,536); with them two-wave
-// blocks lead.
-int backward_default_variant(int64_t n, bool has_v)
+// on, one wave per row below; its workspace is bounded as the forward's (ring
+// groups), and above 2^24 particles the gather kernel takes over.  The same
+// choice serves calls with and without potential weights.
+int backward_default_variant(int64_t n)
 {
     static const int pair_once_big = variant_index("bwd_sym_w8_k2_r8");
     static const int pair_once_large = variant_index("bwd_sym_w4_k2_r8");
     static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
-    static const int pair_once_r8_small = variant_index("bwd_sym_w2_k1_r8");
+    static const int pair_once_r16 = variant_index("bwd_sym_w1_k2_r16");
+    static const int pair_once_split = variant_index("bwd_sym_s2_k2_r8");
     static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int row_1 = variant_index("bwd_row_k1");
@@ -804,17 +849,23 @@ int backward_default_variant(int64_t n, bool has_v)
     // Eight rounds of workgroups (each block's tiles cut into eight times as
     // many chunks as the device holds workgroups, down to one tile; the
     // dispatcher hands the short ones out as slots free up) lead from 6,000
-    // bodies up in forced-variant sweeps on one box: two-wave one-row blocks
-    // below 8,000 (10,000 with potential weights; 6% ahead of one round at
-    // 8,192), then one-wave two-row blocks (4-9% ahead of one round up to
-    // 2^17), 4-wave blocks from 40,000 (10-13% ahead of one round of
-    // two-wave blocks with potential weights at 49,152 and 60,000, 9-11% of
-    // 8-wave ones at 2^17) and 8-wave blocks from 2^18 (3-7% ahead of one
-    // round of them at 2^18 and 2^19).
+    // bodies up in forced-variant sweeps on one box (whole calls, with and
+    // without potential weights): blocks of 128 rows whose two waves split
+    // each tile's steps up to 12,000 (2-7% ahead of one-wave two-row and
+    // two-wave one-row blocks from 7,000 to 10,000, level at 6,000 and
+    // 12,000), then one-wave two-row blocks (4-9% ahead of one round up to
+    // 2^17), in sixteen rounds from 24,000 to 29,999 (one tile per chunk
+    // where eight rounds mix chunks of one and two tiles: 4% ahead at
+    // 24,576, 1% at 28,000, behind at 22,000 and 32,768), 4-wave blocks
+    // from 40,000 (10-13% ahead of one round of two-wave blocks with
+    // potential weights at 49,152 and 60,000, 9-11% of 8-wave ones at 2^17)
+    // and 8-wave blocks from 2^18 (3-7% ahead of one round of them at 2^18
+    // and 2^19).
     if (n >= (1 << 18)) return pair_once_big;
     if (n >= 40000) return pair_once_large;
-    if (n >= (has_v ? 10000 : 8000)) return pair_once_r8;
-    if (n >= 6000) return pair_once_r8_small;
+    if (n >= 24000 && n < 30000) return pair_once_r16;
+    if (n >= 12000) return pair_once_r8;
+    if (n >= 6000) return pair_once_split;
     // one wave per row below 4,800 bodies (two rows from 3,500): 4.7 against
     // 16.1 us per call at 1,024 (split gather and its reduction), 18.3
     // against 21.8 at 4,096 (pair-once and its fold), 34.5 against 29.3 at
@@ -849,7 +900,7 @@ int64_t backward_plan_bytes(int variant, int64_t n, int num_cu, int per_cu)
     if (V.row) return 0;
     if (V.sym) {
         SymPlan pl;
-        if (!sym_plan(n, V.sym_w * 64 * V.sym_k, (int64_t)per_cu * num_cu * V.sym_rounds, V.sym_occ,
+        if (!sym_plan(n, sym_block(V), (int64_t)per_cu * num_cu * V.sym_rounds, V.sym_occ,
                       sym_workspace_budget(n), &pl))
             return -1;
         return (int64_t)pl.bytes();

@@ -473,7 +473,7 @@ void record_tuned_variant(int kind, int64_t n, int index)
     write_cache_locked();
 }
 
-int select_variant(int kind, int64_t n, bool has_v)
+int select_variant(int kind, int64_t n)
 {
     int v = forced_variant(kind);
     if (v >= 0) return v;
@@ -481,7 +481,7 @@ int select_variant(int kind, int64_t n, bool has_v)
     if (v >= 0) return v;
     switch (kind) {
     case NBODY_KIND_FORWARD: return forward_default_variant(n);
-    case NBODY_KIND_BACKWARD: return backward_default_variant(n, has_v);
+    case NBODY_KIND_BACKWARD: return backward_default_variant(n);
     default: return batched_default_variant(n);
     }
 }
@@ -578,7 +578,7 @@ nbody_status nbody_forces_backward(const float *x, const float *m, int64_t n, fl
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     prof_mark((hipStream_t)stream, -1);
-    st = backward_run(select_variant(NBODY_KIND_BACKWARD, n, grad_p != nullptr), dev, x, m, (int)n, eps2, grad_a,
+    st = backward_run(select_variant(NBODY_KIND_BACKWARD, n), dev, x, m, (int)n, eps2, grad_a,
                       grad_p, grad_x, grad_m, (hipStream_t)stream);
     if (st == NBODY_OK) prof_mark((hipStream_t)stream, 2);
     return st;
@@ -743,7 +743,7 @@ nbody_status nbody_leapfrog_adjoint(const float *pos, const float *m, int64_t n,
     nbody_status st = current_device(&dev);
     if (st != NBODY_OK) return st;
     const hipStream_t s = (hipStream_t)stream;
-    const int variant = select_variant(NBODY_KIND_BACKWARD, n, false);
+    const int variant = select_variant(NBODY_KIND_BACKWARD, n);
     // VJP results of variants that cannot take the update in their final
     // reduction
     void *aux = nullptr;

@@ -76,9 +76,8 @@ nbody_status check_launch(const char *what);
 // pair kernel, 1 after it, 2 after the call's last kernel (commits).
 void prof_mark(hipStream_t stream, int which);
 
-// Variant of `kind` for size n: forced, else tuned, else the default (for
-// the backward, has_v tells whether potential weights are given).
-int select_variant(int kind, int64_t n, bool has_v = true);
+// Variant of `kind` for size n: forced, else tuned, else the default.
+int select_variant(int kind, int64_t n);
 // eps2 negative, NaN or infinite (rejected by every entry point).
 bool bad_eps2(float eps2);
 
@@ -123,8 +122,8 @@ nbody_status forward_variant_occupancy(int variant, int *per_cu);
 // ---- backward (vector-Jacobian product of Eq. (gravity))
 int backward_variant_count();
 const char *backward_variant_name(int index);
-// has_v: upstream potential weights (grad_p) are given.
-int backward_default_variant(int64_t n, bool has_v);
+// The same with and without upstream potential weights (grad_p).
+int backward_default_variant(int64_t n);
 // `epi` / `fused` as for forward_run (kLfAdjoint updates; gx, gm still
 // receive the result when the update is not fused).
 nbody_status backward_run(int variant, const Device &dev, const float *x, const float *m,

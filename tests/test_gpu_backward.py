@@ -236,6 +236,23 @@ def test_every_pair_once_variant_without_potential_weights(nb, n):
         nb.set_variant(nb.BACKWARD, -1)
 
 
+@pytest.mark.parametrize("n,variant", [(6000, "bwd_sym_s2_k2_r8"), (9001, "bwd_sym_s2_k2_r8"),
+                                       (11999, "bwd_sym_s2_k2_r8"), (25003, "bwd_sym_w1_k2_r16")])
+def test_mid_n_defaults(nb, n, variant):
+    # the step-split blocks (6,000 to 11,999) and sixteen rounds (24,000 to
+    # 29,999) as the default, with and without potential weights, against
+    # the oracle (one choice for both)
+    dev = need_gpu()
+    names = nb.variant_names(nb.BACKWARD)
+    assert names[nb.selected_variant(nb.BACKWARD, n)] == variant
+    x, m, w, v = _system(n, 73 + n)
+    print(f"[adjoint default] n={n} {variant}", flush=True)
+    for vv in (v, None):
+        gx, gm = _grad(nb, x, m, 1e-3, w, vv, dev)
+        rx, rm = R.forces_vjp(x, m, 1e-3, w, vv)
+        _check(gx, gm, rx, rm, f"default n={n} {'v' if vv is not None else 'no v'}")
+
+
 def test_large_n_defaults(nb):
     # the eight-round defaults from 2^16: at 70,000 bodies (4-wave blocks)
     # against the oracle; at 2^18 + 5 (8-wave blocks, ring groups) against
@@ -276,7 +293,7 @@ def test_adjoint_ring_groups(nb, n, monkeypatch):
     names = nb.variant_names(nb.BACKWARD)
     try:
         for name in ("bwd_sym_w1_k2_o1", "bwd_sym_w2_k2_o1", "bwd_sym_w8_k2_o1", "bwd_sym_w4_k2_r8",
-                     "bwd_sym_w8_k2_r8"):
+                     "bwd_sym_w8_k2_r8", "bwd_sym_s2_k2_r8"):
             nb.set_variant(nb.BACKWARD, names.index(name))
             for slots in (5, 9):
                 monkeypatch.setenv("NBODY_SYM_WORKSPACE", str(16 * n * slots))
