@@ -135,6 +135,21 @@ def test_running_sum_is_aligned(L, n, monkeypatch):
         assert b > 0 and (b - 32 * n) % 256 == 0 and b % 256 != 0, (name, n, b)
 
 
+def test_step_split_blocks_hold_k_rows(L):
+    # bwd_sym_s2_k2_*: two waves share a block of 2 x 64 rows, so the plan
+    # has the blocks, ring offsets and fold slots of the one-wave two-row
+    # blocks: at 16,384 bodies M = 128 blocks and 64 ring offsets, each
+    # block a sequence of 2 + 64 x 2 = 130 tiles.  Eight two-wave
+    # workgroups per CU in eight rounds give 128 chunks per block, sixteen
+    # rounds all 130 (one tile each), as sixteen one-wave workgroups per CU
+    # in eight rounds do.
+    n = 16384
+    assert plan(L, 1, "bwd_sym_s2_k2_r8", n, 8)[0] == (128 + 64) * 16 * n
+    assert plan(L, 1, "bwd_sym_s2_k2_r16", n, 8)[0] == (130 + 64) * 16 * n
+    assert plan(L, 1, "bwd_sym_w1_k2_r8", n, 16)[0] == (130 + 64) * 16 * n
+    assert plan(L, 1, "bwd_sym_w1_k2_r16", n, 16)[0] == (130 + 64) * 16 * n
+
+
 DEFAULTS_CHILD = r"""
 import ctypes, json, sys
 L = ctypes.CDLL(sys.argv[1])
