@@ -525,10 +525,15 @@ int forward_default_variant(int64_t n)
     if (n >= (1 << 16)) return pair_once_4;
     // four-row one-wave blocks lead from about 20,000 (3% at 24,000)
     if (n >= 20000) return pair_once_1;
-    if (n >= 12000) return pair_once_1s;
+    // eight rounds of one-wave blocks of 128 particles from 10,000: below
+    // that one round already cuts every block's sequence into one-tile
+    // chunks (the same plan, the same time), above it one round leaves
+    // chunks of one and two tiles and takes 11% longer (11,000 and 12,000
+    // bodies, forced-variant sweep, same box)
+    if (n >= 10000) return pair_once_1s;
     // one-wave blocks of 128 particles: twice the workgroups of 256-particle
     // blocks, which evens out the one round of workgroups these sizes fill
-    // (3-17% faster from 3,000 to 10,000 bodies, slower from about 12,000)
+    // (3-17% faster from 3,000 to 10,000 bodies)
     // Small n is set by launch latency and the longest dependent chain: one
     // wave per row (two rows from 3,000 bodies), no LDS, no second launch.
     // Kernel 3.4 us at 1,024 bodies against 7.1 us for the one-launch split

@@ -182,8 +182,8 @@ def test_default_table(tmp_path):
     assert r.returncode == 0, r.stderr[-2000:]
     got = json.loads(r.stdout.strip().splitlines()[-1])
     fwd = {1024: "fwd_row_k1", 2999: "fwd_row_k1", 3000: "fwd_row_k2", 4096: "fwd_row_k2",
-           5499: "fwd_row_k2", 5500: "fwd_sym_w1_k2_o1", 10000: "fwd_sym_w1_k2_o1",
-           12000: "fwd_sym_w1_k2_r8", 20000: "fwd_sym_w1_k4_r8", 40000: "fwd_sym_w1_k4_r8",
+           5499: "fwd_row_k2", 5500: "fwd_sym_w1_k2_o1", 9999: "fwd_sym_w1_k2_o1",
+           10000: "fwd_sym_w1_k2_r8", 12000: "fwd_sym_w1_k2_r8", 20000: "fwd_sym_w1_k4_r8", 40000: "fwd_sym_w1_k4_r8",
            65536: "fwd_sym_w4_k4_r8", 1 << 18: "fwd_sym_w4_k4_r8", 1 << 20: "fwd_sym_w8_k4_r8",
            1 << 24: "fwd_sym_w8_k4_r8", (1 << 24) + 1: "fwd_b64_k1_u8_f64sum"}
     # the adjoint (nbody_selected_variant's choice, with or without potential weights)
