@@ -520,9 +520,11 @@ int forward_default_variant(int64_t n)
     // same five ring-group launches), and 4-wave blocks of 1,024 in eight
     // rounds 1-7% ahead from 2^17 to 2^19 (up to 15% ahead of the 8-wave
     // ones there).  Below 2^16 likewise 2-8% from 16,384 to 65,536
-    // (interleaved A/B in one process).
+    // (interleaved A/B in one process).  The 4-wave blocks lead the
+    // one-wave four-row ones from 40,000 bodies (1-5% from 40,000 to
+    // 60,000, 3-5% behind at 36,000; forced-variant sweep, same box).
     if (n >= (1 << 20)) return pair_once_8;
-    if (n >= (1 << 16)) return pair_once_4;
+    if (n >= 40000) return pair_once_4;
     // four-row one-wave blocks lead from about 20,000 (3% at 24,000)
     if (n >= 20000) return pair_once_1;
     // eight rounds of one-wave blocks of 128 particles from 10,000: below

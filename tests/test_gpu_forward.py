@@ -470,3 +470,22 @@ def test_every_pair_once_variant_with_and_without_potential(nb, n):
             assert e_mag <= 1e-4 and e_vec <= 1e-4, name
     finally:
         nb.set_variant(nb.FORWARD, -1)
+
+
+@pytest.mark.parametrize("n,variant", [(9999, "fwd_sym_w1_k2_o1"), (10000, "fwd_sym_w1_k2_r8"),
+                                       (39999, "fwd_sym_w1_k4_r8"), (45001, "fwd_sym_w4_k4_r8")])
+def test_default_band_edges(nb, n, variant):
+    # The default at the edges of its size bands against the oracle (2,048
+    # seeded rows above 16,384 bodies), and the same a without p.
+    dev = need_gpu()
+    names = nb.variant_names(nb.FORWARD)
+    assert names[nb.selected_variant(nb.FORWARD, n)] == variant
+    x, m, rows, ar, pr = _pair_once_case(n)
+    xd, md = to_dev(x, dev), to_dev(m, dev)
+    sel = slice(None) if rows is None else rows
+    print(f"[default band] {variant} n={n}", flush=True)
+    a_p, p = nb.forces(xd, md, 1e-4)
+    a_n, _ = nb.forces(xd, md, 1e-4, potential=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a_p, a_n)
+    assert_parity(host(a_p)[sel], host(p)[sel], ar, pr, label=f"default {variant} n={n}")
