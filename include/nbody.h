@@ -94,7 +94,7 @@ const char *nbody_last_error(void);
  * Arithmetic: float32 with fused multiply-add, hardware reciprocal square
  * root, and partial sums folded per j-tile (two-level accumulation).
  * The result is bitwise reproducible for a fixed n, variant and device.
- * Kernels: for 5,500 <= n <= 2^24 the default variant evaluates each
+ * Kernels: for 4,500 <= n <= 2^24 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair), in blocks of P = 2048 particles from
  * 2^20 up, 1024 from 40,000, 256 from 20,000 and 128 below.  Each block meets
@@ -102,7 +102,7 @@ const char *nbody_last_error(void);
  * per group, each followed by a launch that adds the group's partial sums
  * to a float64 running sum per particle, so the library workspace stays at
  * most 1 GiB up to n = 2^22 (256 n bytes above; 0.97 GiB at n = 2^20).
- * Outside that range the default evaluates every ordered pair: below 5,500
+ * Outside that range the default evaluates every ordered pair: below 4,500
  * in one launch with one wave per row (two rows from 3,000), its lanes
  * splitting j and their sums added by a fixed in-register butterfly (no
  * workspace); above 2^24 gathered per row with j-splits, float64 row sums

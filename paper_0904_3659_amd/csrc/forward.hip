@@ -493,7 +493,7 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once kernel wins from about 5,500 particles
+// Measured on MI355X: the pair-once kernel wins from about 4,500 particles
 // on, one wave per row below.  Its
 // workspace is bounded (ring groups, about 1 GiB up to 2^22 particles,
 // 256 n bytes above); beyond 2^24 particles, where a group would hold very
@@ -539,13 +539,15 @@ int forward_default_variant(int64_t n)
     // Small n is set by launch latency and the longest dependent chain: one
     // wave per row (two rows from 3,000 bodies), no LDS, no second launch.
     // Kernel 3.4 us at 1,024 bodies against 7.1 us for the one-launch split
-    // gather.  Against the pair-once kernel and its fold the row kernel
-    // leads a plain call up to about 6,500 bodies (18.3 against 21.1 us at
-    // 6,000) but a leap-frog step, whose update the pair-once fold applies
-    // in place and the row kernel needs a launch for, only up to about
-    // 4,500 (19.7 against 17.3 us at 5,000); both use one choice, so that a
+    // gather.  Against the pair-once kernel and its fold (forced variants,
+    // same box) the row kernel leads up to 4,000 bodies (plain calls 17.3
+    // against 20.6 us, leap-frog steps 13.9 against 16.4 us), is level with
+    // it for plain calls with the potential at 4,500 and behind from 5,000
+    // (22.5 against 22.0 us); a leap-frog step, whose update the pair-once
+    // fold applies in place and the row kernel needs a launch for, is 6-14%
+    // faster pair-once from 4,500 to 5,000.  Both use one choice, so that a
     // leap-frog call stays bitwise the composed calls.
-    if (n >= 5500) return pair_once_small;
+    if (n >= 4500) return pair_once_small;
     return n >= 3000 ? row_2 : row_1;
 }
 

@@ -234,10 +234,10 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 1 << 22)].startswith("fwd_sym")
     assert names[nb.selected_variant(nb.FORWARD, 1 << 24)].startswith("fwd_sym")
     assert not names[nb.selected_variant(nb.FORWARD, (1 << 24) + 1)].startswith("fwd_sym")
-    # one wave per row (two rows from 3,000 bodies) below 5,500 bodies
+    # one wave per row (two rows from 3,000 bodies) below 4,500 bodies
     assert names[nb.selected_variant(nb.FORWARD, 1024)] == "fwd_row_k1"
     assert names[nb.selected_variant(nb.FORWARD, 4096)] == "fwd_row_k2"
-    assert names[nb.selected_variant(nb.FORWARD, 5500)].startswith("fwd_sym")
+    assert names[nb.selected_variant(nb.FORWARD, 4500)].startswith("fwd_sym")
     b = nb.variant_names(nb.BACKWARD)
     assert b[nb.selected_variant(nb.BACKWARD, 1024)] == "bwd_row_k1"
     assert b[nb.selected_variant(nb.BACKWARD, 4096)] == "bwd_row_k2"
