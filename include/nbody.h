@@ -185,14 +185,14 @@ nbody_status nbody_forces_ex(const float *x, const float *m, int64_t n, float ep
  * grad_a or grad_p may be NULL (meaning zero).  grad_m may be NULL (skip).
  * grad_x: [n][3] out, grad_m: [n] out.  Same arithmetic, determinism and
  * error rules as nbody_forces; NULL grad_x with n > 0 -> INVALID_ARGUMENT.
- * Kernels: for 4,800 <= n <= 2^24 the default variant evaluates each
+ * Kernels: for 4,000 <= n <= 2^24 the default variant evaluates each
  * unordered pair once (the x-gradient term is antisymmetric in the pair),
  * for blocks of P = 1024 particles from 2^18, 512 from 40,000 and 128
- * below (from 6,000 to 11,999 two waves share a block's rows and split
+ * below (from 4,000 to 11,999 two waves share a block's rows and split
  * each tile's steps), with the ring groups and bounded workspace of the
  * pair-once forward (at most 1 GiB up to n = 2^22).  With grad_p NULL it
  * does not form the potential-weight terms (with the same variant, bitwise
- * the result of zero weights); the default variant is the same.  Below 4,800 one
+ * the result of zero weights); the default variant is the same.  Below 4,000 one
  * launch with one wave per row (two rows from 3,500) evaluates every
  * ordered pair (no workspace); above 2^24 every ordered pair is gathered
  * per row.

@@ -830,7 +830,7 @@ static int variant_index(const char *name)
     return 0;
 }
 
-// Measured on MI355X: the pair-once adjoint wins from about 4,800 particles
+// Measured on MI355X: the pair-once adjoint wins from about 4,000 particles
 // on, one wave per row below; its workspace is bounded as the forward's (ring
 // groups), and above 2^24 particles the gather kernel takes over.  The same
 // choice serves calls with and without potential weights.
@@ -841,19 +841,20 @@ int backward_default_variant(int64_t n)
     static const int pair_once_r8 = variant_index("bwd_sym_w1_k2_r8");
     static const int pair_once_r16 = variant_index("bwd_sym_w1_k2_r16");
     static const int pair_once_split = variant_index("bwd_sym_s2_k2_r8");
-    static const int pair_once_small = variant_index("bwd_sym_w2_k1_o1");
     static const int gather = variant_index("bwd_b256_k1_u8");
     static const int row_1 = variant_index("bwd_row_k1");
     static const int row_2 = variant_index("bwd_row_k2");
     if (n > (1 << 24)) return gather;
     // Eight rounds of workgroups (each block's tiles cut into eight times as
     // many chunks as the device holds workgroups, down to one tile; the
-    // dispatcher hands the short ones out as slots free up) lead from 6,000
+    // dispatcher hands the short ones out as slots free up) lead from 4,000
     // bodies up in forced-variant sweeps on one box (whole calls, with and
     // without potential weights): blocks of 128 rows whose two waves split
-    // each tile's steps up to 12,000 (2-7% ahead of one-wave two-row and
-    // two-wave one-row blocks from 7,000 to 10,000, level at 6,000 and
-    // 12,000), then one-wave two-row blocks (4-9% ahead of one round up to
+    // each tile's steps up to 12,000 (4-6% ahead of the two-row row kernel
+    // at 4,000, level with it at 3,500; 5-10% ahead of one round of two-wave
+    // one-row blocks from 4,500 to 5,600; 2-7% ahead of one-wave two-row and
+    // two-wave one-row blocks in eight rounds from 7,000 to 10,000, level at
+    // 6,000 and 12,000), then one-wave two-row blocks (4-9% ahead of one round up to
     // 2^17), in sixteen rounds from 24,000 to 29,999 (one tile per chunk
     // where eight rounds mix chunks of one and two tiles: 4% ahead at
     // 24,576, 1% at 28,000, behind at 22,000 and 32,768), 4-wave blocks
@@ -865,12 +866,10 @@ int backward_default_variant(int64_t n)
     if (n >= 40000) return pair_once_large;
     if (n >= 24000 && n < 30000) return pair_once_r16;
     if (n >= 12000) return pair_once_r8;
-    if (n >= 6000) return pair_once_split;
-    // one wave per row below 4,800 bodies (two rows from 3,500): 4.7 against
-    // 16.1 us per call at 1,024 (split gather and its reduction), 18.3
-    // against 21.8 at 4,096 (pair-once and its fold), 34.5 against 29.3 at
-    // 6,000
-    if (n >= 4800) return pair_once_small;
+    if (n >= 4000) return pair_once_split;
+    // one wave per row below 4,000 bodies (two rows from 3,500): 4.7 against
+    // 16.1 us per call at 1,024 (split gather and its reduction), 13.3-14.4
+    // against 21.5-22.0 at 1,500 (pair-once and its fold)
     return n >= 3500 ? row_2 : row_1;
 }
 

@@ -236,10 +236,11 @@ def test_every_pair_once_variant_without_potential_weights(nb, n):
         nb.set_variant(nb.BACKWARD, -1)
 
 
-@pytest.mark.parametrize("n,variant", [(6000, "bwd_sym_s2_k2_r8"), (9001, "bwd_sym_s2_k2_r8"),
+@pytest.mark.parametrize("n,variant", [(3999, "bwd_row_k2"), (4000, "bwd_sym_s2_k2_r8"),
+                                       (4801, "bwd_sym_s2_k2_r8"), (9001, "bwd_sym_s2_k2_r8"),
                                        (11999, "bwd_sym_s2_k2_r8"), (25003, "bwd_sym_w1_k2_r16")])
 def test_mid_n_defaults(nb, n, variant):
-    # the step-split blocks (6,000 to 11,999) and sixteen rounds (24,000 to
+    # the step-split blocks (4,000 to 11,999) and sixteen rounds (24,000 to
     # 29,999) as the default, with and without potential weights, against
     # the oracle (one choice for both)
     dev = need_gpu()

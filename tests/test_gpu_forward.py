@@ -240,8 +240,8 @@ def test_default_variant_choice(nb):
     assert names[nb.selected_variant(nb.FORWARD, 4500)].startswith("fwd_sym")
     b = nb.variant_names(nb.BACKWARD)
     assert b[nb.selected_variant(nb.BACKWARD, 1024)] == "bwd_row_k1"
-    assert b[nb.selected_variant(nb.BACKWARD, 4096)] == "bwd_row_k2"
-    assert b[nb.selected_variant(nb.BACKWARD, 4800)].startswith("bwd_sym")
+    assert b[nb.selected_variant(nb.BACKWARD, 3999)] == "bwd_row_k2"
+    assert b[nb.selected_variant(nb.BACKWARD, 4000)].startswith("bwd_sym")
 
 
 def test_profile_hook(nb):

@@ -172,7 +172,7 @@ def test_default_table(tmp_path):
     import sys
     if not os.path.exists(B.LIBRARY):
         pytest.skip("libnbody.so not built (run __graft_entry__.build())")
-    sizes = [1024, 2999, 3000, 4096, 4499, 4500, 4800, 5499, 5500, 5999, 6000, 8000, 9999, 10000, 11999,
+    sizes = [1024, 2999, 3000, 3999, 4000, 4096, 4499, 4500, 4800, 5499, 5500, 5999, 6000, 8000, 9999, 10000, 11999,
              12000, 20000, 23999, 24000, 29999, 30000, 39999, 40000, 65536, 1 << 18, 1 << 20, 1 << 24,
              (1 << 24) + 1]
     env = dict(os.environ, NBODY_TUNE_CACHE=str(tmp_path / "none.json"))
@@ -188,8 +188,9 @@ def test_default_table(tmp_path):
            39999: "fwd_sym_w1_k4_r8", 40000: "fwd_sym_w4_k4_r8", 65536: "fwd_sym_w4_k4_r8", 1 << 18: "fwd_sym_w4_k4_r8", 1 << 20: "fwd_sym_w8_k4_r8",
            1 << 24: "fwd_sym_w8_k4_r8", (1 << 24) + 1: "fwd_b64_k1_u8_f64sum"}
     # the adjoint (nbody_selected_variant's choice, with or without potential weights)
-    bwd = {1024: "bwd_row_k1", 3000: "bwd_row_k1", 4096: "bwd_row_k2", 4800: "bwd_sym_w2_k1_o1",
-           5999: "bwd_sym_w2_k1_o1", 6000: "bwd_sym_s2_k2_r8", 9999: "bwd_sym_s2_k2_r8",
+    bwd = {1024: "bwd_row_k1", 3000: "bwd_row_k1", 3999: "bwd_row_k2", 4000: "bwd_sym_s2_k2_r8",
+           4096: "bwd_sym_s2_k2_r8", 4800: "bwd_sym_s2_k2_r8", 5999: "bwd_sym_s2_k2_r8",
+           6000: "bwd_sym_s2_k2_r8", 9999: "bwd_sym_s2_k2_r8",
            11999: "bwd_sym_s2_k2_r8", 12000: "bwd_sym_w1_k2_r8", 20000: "bwd_sym_w1_k2_r8",
            23999: "bwd_sym_w1_k2_r8", 24000: "bwd_sym_w1_k2_r16", 29999: "bwd_sym_w1_k2_r16",
            30000: "bwd_sym_w1_k2_r8", 40000: "bwd_sym_w4_k2_r8", 65536: "bwd_sym_w4_k2_r8",
