@@ -394,7 +394,7 @@ class Leapfrog(torch.autograd.Function):
 # 64-step gradient with checkpoints every 8 steps takes 11-19% less time
 # with graphs from 128 to 2,048 bodies, where a step's kernels take a few
 # microseconds and the host's launches show; from 3,000 bodies on the
-# eager launches are faster (5% at 3,000, 18% at 4,096, 3% at 16,384): a
+# eager launches are faster (5% at 3,000, 18% at 4,096, 2-8% at 16,384): a
 # graph's kernel nodes start a little later than launches into a stream,
 # and the eager reverse pass recomputes positions as far ahead of the sweep
 # as the host gets (a tensor per segment) where the graphs have two fixed
