@@ -103,6 +103,27 @@ def test_every_variant(nb):
         nb.set_variant(nb.BACKWARD, -1)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 129])
+def test_every_variant_tiny(nb, n):
+    # every adjoint variant, forced, at a few particles: one particle gives
+    # exactly zero; otherwise a single ragged tile or block against the oracle
+    dev = need_gpu()
+    x, m, w, v = _system(n, 300 + n)
+    rx, rm = R.forces_vjp(x, m, 1e-3, w, v)
+    names = nb.variant_names(nb.BACKWARD)
+    try:
+        for k in range(nb.variant_count(nb.BACKWARD)):
+            print(f"[tiny] {names[k]} n={n}", flush=True)
+            nb.set_variant(nb.BACKWARD, k)
+            gx, gm = _grad(nb, x, m, 1e-3, w, v, dev)
+            if n == 1:
+                assert not gx.any() and not gm.any(), names[k]
+            else:
+                _check(gx, gm, rx, rm, f"{names[k]} n={n}")
+    finally:
+        nb.set_variant(nb.BACKWARD, -1)
+
+
 def test_autograd_function(nb):
     dev = need_gpu()
     x, m, w, v = _system(800, 11)

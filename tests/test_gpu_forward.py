@@ -147,6 +147,29 @@ def test_every_variant(nb, n):
         nb.set_variant(nb.FORWARD, -1)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 129])
+def test_every_variant_tiny(nb, n):
+    # every variant, forced, at a few particles: one particle gives exactly
+    # zero; otherwise a single ragged tile or block against the oracle
+    dev = need_gpu()
+    g = np.random.default_rng(200 + n)
+    x = g.standard_normal((n, 3)).astype(np.float32)
+    m = g.uniform(0.1, 1.0, n).astype(np.float32)
+    ar, pr = R.forces(x, m, 1e-3)
+    names = nb.variant_names(nb.FORWARD)
+    try:
+        for v in range(nb.variant_count(nb.FORWARD)):
+            print(f"[tiny] {names[v]} n={n}", flush=True)
+            nb.set_variant(nb.FORWARD, v)
+            a, p = _run(nb, x, m, 1e-3, dev)
+            if n == 1:
+                assert a.tolist() == [[0.0, 0.0, 0.0]] and p.tolist() == [0.0], names[v]
+            else:
+                assert_parity(a, p, ar, pr, label=f"{names[v]} n={n}")
+    finally:
+        nb.set_variant(nb.FORWARD, -1)
+
+
 def test_potential_optional_and_out(nb):
     dev = need_gpu()
     w = inputs.plummer_1k()
