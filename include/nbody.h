@@ -97,7 +97,7 @@ const char *nbody_last_error(void);
  * Kernels: for 4,500 <= n <= 2^24 the default variant evaluates each
  * unordered pair once and gives the term to both particles (the softened
  * force is antisymmetric in the pair), in blocks of P = 2048 particles from
- * 2^20 up, 1024 from 40,000, 256 from 20,000 and 128 below.  Each block meets
+ * 2^20 up, 1024 from 40,000, 256 from 18,000 and 128 below.  Each block meets
  * the blocks after it on a ring; the ring offsets run in groups, one launch
  * per group, each followed by a launch that adds the group's partial sums
  * to a float64 running sum per particle, so the library workspace stays at

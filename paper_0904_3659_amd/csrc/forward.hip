@@ -525,8 +525,9 @@ int forward_default_variant(int64_t n)
     // 60,000, 3-5% behind at 36,000; forced-variant sweep, same box).
     if (n >= (1 << 20)) return pair_once_8;
     if (n >= 40000) return pair_once_4;
-    // four-row one-wave blocks lead from about 20,000 (3% at 24,000)
-    if (n >= 20000) return pair_once_1;
+    // four-row one-wave blocks lead from about 18,000 (2% at 18,000 and
+    // 22,000, 3% at 24,000; 1-2% behind at 16,384)
+    if (n >= 18000) return pair_once_1;
     // eight rounds of one-wave blocks of 128 particles from 10,000: below
     // that one round already cuts every block's sequence into one-tile
     // chunks (the same plan, the same time), above it one round leaves

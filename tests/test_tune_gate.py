@@ -173,7 +173,7 @@ def test_default_table(tmp_path):
     if not os.path.exists(B.LIBRARY):
         pytest.skip("libnbody.so not built (run __graft_entry__.build())")
     sizes = [1024, 2999, 3000, 3999, 4000, 4096, 4499, 4500, 4800, 5499, 5500, 5999, 6000, 8000, 9999, 10000, 11999,
-             12000, 20000, 23999, 24000, 29999, 30000, 39999, 40000, 65536, 1 << 18, 1 << 20, 1 << 24,
+             12000, 17999, 18000, 20000, 23999, 24000, 29999, 30000, 39999, 40000, 65536, 1 << 18, 1 << 20, 1 << 24,
              (1 << 24) + 1]
     env = dict(os.environ, NBODY_TUNE_CACHE=str(tmp_path / "none.json"))
     env.pop("NBODY_VARIANT", None)
@@ -184,7 +184,8 @@ def test_default_table(tmp_path):
     fwd = {1024: "fwd_row_k1", 2999: "fwd_row_k1", 3000: "fwd_row_k2", 4096: "fwd_row_k2",
            4499: "fwd_row_k2", 4500: "fwd_sym_w1_k2_o1", 5499: "fwd_sym_w1_k2_o1",
            5500: "fwd_sym_w1_k2_o1", 9999: "fwd_sym_w1_k2_o1",
-           10000: "fwd_sym_w1_k2_r8", 12000: "fwd_sym_w1_k2_r8", 20000: "fwd_sym_w1_k4_r8",
+           10000: "fwd_sym_w1_k2_r8", 12000: "fwd_sym_w1_k2_r8", 17999: "fwd_sym_w1_k2_r8",
+           18000: "fwd_sym_w1_k4_r8", 20000: "fwd_sym_w1_k4_r8",
            39999: "fwd_sym_w1_k4_r8", 40000: "fwd_sym_w4_k4_r8", 65536: "fwd_sym_w4_k4_r8", 1 << 18: "fwd_sym_w4_k4_r8", 1 << 20: "fwd_sym_w8_k4_r8",
            1 << 24: "fwd_sym_w8_k4_r8", (1 << 24) + 1: "fwd_b64_k1_u8_f64sum"}
     # the adjoint (nbody_selected_variant's choice, with or without potential weights)
