@@ -64,15 +64,18 @@ def test_checkpointing_is_bitwise_neutral(nb, n, steps, ks):
                 assert torch.equal(a, b), f"checkpoint_every={k} graphs={graphs}"
 
 
-def test_gradient_matches_oracle_sweep(nb):
+@pytest.mark.parametrize("n", [2048, 5000])
+def test_gradient_matches_oracle_sweep(nb, n):
+    # 2,048 bodies: row-per-wave kernels and HIP-graph segments; 5,000: the
+    # pair-once forward, the step-split pair-once adjoint and eager launches
     dev = need_gpu()
-    x, v, m, u = _case(2048, 2)
-    _, gx, gv, gm = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 8, dev)
+    x, v, m, u = _case(n, 2)
+    _, gx, gv, gm = _grads(nb, x, v, m, u, 1e-4, 1e-3, 64, 8, dev, graphs=None)
     rx, rv, rm = R.leapfrog_vjp(x, v, m, 1e-4, 1e-3, 64, u)
     for g, r, name in ((gx, rx, "x0"), (gv, rv, "v0"), (gm, rm, "m")):
         g = host(g)
         e = np.abs(g - r).max() / np.abs(r).max()
-        print(f"[parity] leapfrog grad {name} normwise {e:.2e}", flush=True)
+        print(f"[parity] leapfrog grad n={n} {name} normwise {e:.2e}", flush=True)
         assert e <= 1e-3, name
 
 
